@@ -1,0 +1,124 @@
+"""Seeded synthetic initial states, shared by the engine's tests, the benchmark
+and the oracle checks.
+
+This module only draws random numbers and lays out a lattice: it contains none
+of the method's arithmetic (no distances, no forces, no integration).  The
+paper simulates self-generated fluids (Models section: LJ and patchy systems at
+given number density and temperature); these states stand in for them.
+
+Recipe (fixed draw order, numpy PCG64 ``default_rng(seed + 1000 * attempt)``):
+  1. simple-cubic lattice with n = ceil(N^(1/3)) sites per side and spacing
+     L/n, sites at (k + 1/2) * L/n, the first N sites in x-fastest order;
+  2. jitter U[-0.05, 0.05] sigma per component, then wrapped into [0, L);
+  3. velocities N(0, sqrt(T/m)) per component, mean removed, rescaled so that
+     sum m v^2 / (3N - 3) = T exactly;
+  4. patchy only: quaternions from 4 standard normals, normalised (uniform on
+     SO(3)); angular momenta N(0, sqrt(I T)) per component.
+``attempt`` lets a caller redraw the jitter when a state is rejected (e.g.
+because a pair distance sits within 1e-9 sigma of a cut-off).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, replace
+
+import numpy as np
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    pot: str                # "lj" or "patchy"
+    n: int
+    rho: float
+    temp: float
+    rcut: float
+    skin: float = 0.3
+    dt: float = 0.001
+    steps: int = 100
+    eps: float = 1.0
+    sigma: float = 1.0
+    mass: float = 1.0
+    # patchy only
+    eps_p: float = 1.0
+    patch_w: float = 0.12
+    patch_delta: float = 0.5
+    patch_rcut: float = 0.75
+    inertia: float = 1.0
+    max_neighbors: int = 0  # 0: choose from the density
+
+    @property
+    def box(self) -> float:
+        return (self.n / self.rho) ** (1.0 / 3.0)
+
+    @property
+    def rv(self) -> float:
+        return self.rcut + self.skin
+
+    def expected_neighbors(self) -> float:
+        """Mean full-list length of a uniform fluid, rho * 4/3 pi r_v^3."""
+        return self.rho * 4.0 / 3.0 * math.pi * self.rv ** 3
+
+    def list_capacity(self) -> int:
+        if self.max_neighbors:
+            return self.max_neighbors
+        m = self.expected_neighbors()
+        # uniform-fluid mean plus a wide margin for fluctuations; multiple of 16
+        cap = int(math.ceil((1.5 * m + 8 * math.sqrt(m) + 16) / 16.0) * 16)
+        return cap
+
+    def with_(self, **kw) -> "Workload":
+        return replace(self, **kw)
+
+
+# The systems studied (densities, temperatures and cut-offs of the LJ and
+# patchy fluids; see the workload recipe in the design notes).
+WORKLOADS = {
+    "lj_small": Workload("lj_small", "lj", 4096, 0.8, 1.5, 2.5, steps=100),
+    "lj_many": Workload("lj_many", "lj", 262144, 0.8, 1.5, 2.5, steps=1000),
+    "lj_many_dense": Workload("lj_many_dense", "lj", 262144, 1.0, 1.5, 3.0, steps=1000),
+    "patchy": Workload("patchy", "patchy", 131072, 0.5, 0.2, 1.5, steps=1000),
+    "lj_precision": Workload("lj_precision", "lj", 1048576, 0.8, 1.0, 2.5, dt=0.005,
+                             steps=10000),
+}
+
+
+@dataclass
+class State:
+    x: np.ndarray          # (N, 3) float64 positions in [0, L)
+    v: np.ndarray          # (N, 3) float64 velocities
+    q: np.ndarray | None   # (N, 4) float64 unit quaternions (w, x, y, z), patchy
+    angmom: np.ndarray | None  # (N, 3) float64 angular momenta, patchy
+    box: float
+    seed: int
+    attempt: int
+
+
+def lattice(n: int, box: float) -> np.ndarray:
+    m = int(math.ceil(round(n ** (1.0 / 3.0), 12)))
+    while m ** 3 < n:
+        m += 1
+    a = box / m
+    k = np.arange(n)
+    ix, iy, iz = k % m, (k // m) % m, k // (m * m)
+    return (np.stack([ix, iy, iz], axis=1).astype(np.float64) + 0.5) * a
+
+
+def make_state(w: Workload, seed: int, attempt: int = 0) -> State:
+    rng = np.random.default_rng(seed + 1000 * attempt)
+    L = w.box
+    n = w.n
+    x = lattice(n, L) + rng.uniform(-0.05, 0.05, size=(n, 3)) * w.sigma
+    x = np.mod(x, L)
+    x[x >= L] -= L
+    v = rng.normal(0.0, math.sqrt(w.temp / w.mass), size=(n, 3))
+    v -= v.mean(axis=0)
+    dof = 3 * n - 3
+    t_now = (w.mass * (v * v).sum()) / dof
+    v *= math.sqrt(w.temp / t_now)
+    q = am = None
+    if w.pot == "patchy":
+        q = rng.normal(size=(n, 4))
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        am = rng.normal(0.0, math.sqrt(w.inertia * w.temp), size=(n, 3))
+    return State(x=x, v=v, q=q, angmom=am, box=L, seed=seed, attempt=attempt)
