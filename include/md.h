@@ -1,0 +1,183 @@
+/*
+ * libmd -- short-range pair-force molecular dynamics on one MI355X (gfx950).
+ *
+ * The engine implements the force step compared in Rovigatti, Sulc, Reguly and
+ * Romano, "A comparison between parallelization approaches in molecular
+ * dynamics simulations on GPUs", in both of its decompositions:
+ *
+ *   MD_MODE_VERTEX  one thread per particle walks that particle's Verlet list
+ *                   and sums every pair itself; each pair is evaluated twice
+ *                   and no memory is written concurrently (Methods section,
+ *                   "vertex-based" approach; Fig. 1 left).
+ *   MD_MODE_EDGE    one thread per potentially non-zero interaction (one entry
+ *                   of the half list, sum_i n_i / 2 threads) evaluates the pair
+ *                   once and adds +F to one particle and -F to the other with
+ *                   atomic operations, skipped when the pair force is exactly
+ *                   zero (Methods section, "edge-based" approach; Fig. 1 right).
+ *
+ * Both read Verlet lists of radius r_v = r_c + r_s built with a cell algorithm
+ * (Methods section), and are followed by an FP64 velocity-Verlet update
+ * (Methods section: positions and momenta are integrated in double precision;
+ * forces may be computed in single precision).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns md_status; nothing aborts or throws across the ABI.
+ *     Argument errors are detected on the host before any HIP call.
+ *   - Device buffers are owned by the caller (see md_create); libmd owns only the
+ *     handle and a few bytes of host state.  libmd never calls hipMalloc.
+ *   - Work is enqueued on the caller's HIP stream.  Functions marked "async"
+ *     return before the GPU finishes; functions marked "syncs" wait for the
+ *     stream and report sticky device-side errors (list overflow, non-finite
+ *     forces) that earlier async calls raised.
+ *   - Host arrays are AoS in the caller's original particle order: x[3*i+c],
+ *     q[4*i+k] with q = (w, x, y, z) a unit Hamilton quaternion.
+ *   - Units: lengths in sigma, energies in eps, masses in m; the box is cubic
+ *     and periodic with side `box`, positions in [0, box).
+ *   - A handle is not thread-safe; distinct handles on distinct streams are.
+ */
+#ifndef LIBMD_H
+#define LIBMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct md_system md_system; /* opaque handle */
+
+typedef enum {
+    MD_OK = 0,
+    MD_ERR_INVALID_ARG = -1,       /* bad parameter or NULL pointer            */
+    MD_ERR_BUFFER_TOO_SMALL = -2,  /* caller buffer smaller than md_query_sizes */
+    MD_ERR_HIP = -3,               /* a HIP runtime call failed                 */
+    MD_ERR_NEIGHBOR_OVERFLOW = -4, /* a Verlet list exceeded max_neighbors      */
+    MD_ERR_BOX_TOO_SMALL = -5,     /* box <= 2 r_v: minimum image not unique    */
+    MD_ERR_NONFINITE = -6,         /* a force or position became NaN/Inf        */
+    MD_ERR_STATE = -7              /* call out of order (e.g. no state set)     */
+} md_status;
+
+typedef enum { MD_POT_LJ = 0, MD_POT_PATCHY = 1 } md_potential;
+typedef enum { MD_MODE_VERTEX = 0, MD_MODE_EDGE = 1 } md_mode;
+
+/* Arithmetic of the pair forces.  Positions, velocities and the integrator are
+ * FP64 in every variant (Methods section, mixed precision). */
+typedef enum {
+    MD_PREC_FP64 = 0,        /* pair maths and accumulation in FP64                */
+    MD_PREC_FP32_F64ACC = 1, /* pair maths in FP32 from an FP64 separation, sums FP64 */
+    MD_PREC_FP32_KAHAN = 2   /* pair maths in FP32, compensated FP32 sums           */
+} md_precision;
+
+typedef struct {
+    int32_t n;             /* number of particles, >= 2                              */
+    int32_t pot;           /* md_potential                                           */
+    int32_t prec;          /* md_precision                                           */
+    int32_t max_neighbors; /* Verlet-list capacity per particle (full list), >= 1    */
+    double box;            /* cubic box side L; must exceed 2 (rcut + skin)          */
+    double eps, sigma;     /* LJ (Eq. 1) or WCA core strength and diameter           */
+    double rcut;           /* interaction cut-off r_c                                */
+    double skin;           /* Verlet skin r_s >= 0; lists hold pairs with r < r_c+r_s */
+    double mass;           /* particle mass > 0                                      */
+    double dt;             /* time step > 0                                          */
+    /* patchy particles (MD_POT_PATCHY) only */
+    double eps_p;          /* patch-patch strength                                   */
+    double patch_w;        /* Gaussian width of the patch attraction                 */
+    double patch_delta;    /* distance of a patch from the particle centre           */
+    double patch_rcut;     /* patch-patch cut-off; <= 0 means none                    */
+    double inertia;        /* isotropic moment of inertia > 0                        */
+} md_params;
+
+typedef struct {
+    uint64_t state_bytes;     /* persistent particle state                       */
+    uint64_t workspace_bytes; /* cell lists, Verlet lists, scratch               */
+    uint64_t alignment;       /* required alignment of both buffers (bytes)      */
+} md_sizes;
+
+typedef struct {
+    int64_t steps;          /* MD steps taken by md_step                           */
+    int64_t rebuilds;       /* Verlet-list builds, including the initial one       */
+    int64_t pairs;          /* half-list entries |E| at the last build             */
+    int32_t max_list_len;   /* longest full list at the last build                 */
+    int32_t n_cells;        /* cells per box side                                  */
+} md_stats_t;
+
+/* Sizes of the two device buffers a system needs (pure host, no HIP call).
+ * Returns MD_ERR_INVALID_ARG / MD_ERR_BOX_TOO_SMALL for bad parameters. */
+md_status md_query_sizes(const md_params* p, md_sizes* out);
+
+/* Create a system on the current HIP device.  d_state and d_workspace are
+ * device buffers of at least the sizes md_query_sizes reports, aligned to
+ * `alignment`; they are borrowed and must outlive the handle.  hip_stream is a
+ * hipStream_t (NULL = default stream) on which all work of the handle runs.
+ * Validation as md_query_sizes, plus MD_ERR_BUFFER_TOO_SMALL. */
+md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes,
+                    void* d_workspace, uint64_t workspace_bytes, void* hip_stream,
+                    md_system** out);
+
+/* Upload particle state (host AoS, original order).  x and v are n*3 doubles;
+ * q (n*4) and angmom (n*3) are required for MD_POT_PATCHY and ignored for LJ.
+ * Positions are wrapped into [0, box).  Invalidates lists and forces.  Syncs. */
+md_status md_set_state(md_system* s, const double* x, const double* v,
+                       const double* q, const double* angmom);
+
+/* Cell-list counting sort (Methods section: cell filling, one particle per
+ * thread): bins particles into cells of side >= r_v, sorts them by cell (and
+ * by original id inside a cell) and reorders the particle arrays into that
+ * order.  Async. */
+md_status md_build_cells(md_system* s);
+
+/* Verlet-list build (Methods section: one particle per thread over the
+ * neighbouring cells): full lists of all j with r_ij < r_v for the vertex
+ * kernel, the half list (pairs counted once) for the edge kernel, and the
+ * reference positions for the rebuild test.  Requires md_build_cells first.
+ * Overflow of max_neighbors is reported by the next syncing call.  Async. */
+md_status md_build_neighbors(md_system* s);
+
+/* Pair forces (and torques for patchy) at the current positions with the
+ * given decomposition.  Requires built lists.  Async. */
+md_status md_forces(md_system* s, int32_t mode);
+
+/* nsteps velocity-Verlet steps (rotational velocity Verlet for patchy) with
+ * forces from `mode`.  Per step: half kick, drift, wrap; if any particle moved
+ * more than skin/2 since the last build the cells and lists are rebuilt on
+ * the device (no host round trip); forces; half kick.  Computes forces first
+ * if they are not valid.  Syncs at the end and reports device errors. */
+md_status md_step(md_system* s, int32_t nsteps, int32_t mode);
+
+/* Kinetic energy (translational + rotational), potential energy
+ * sum_{i<j} V_ij and virial sum_{i<j} r_ij . F_j, reduced in FP64 in a fixed
+ * order (deterministic for a given particle order).  Any output may be NULL.
+ * Syncs. */
+md_status md_energy(md_system* s, double* e_kin, double* e_pot, double* virial);
+
+/* Per-particle potential energies e_i = 1/2 sum_j V_ij (n doubles, original
+ * order), evaluated with the configured precision.  Syncs. */
+md_status md_particle_energies(md_system* s, double* e);
+
+/* Download state in original order; any pointer may be NULL.  x, v, f, angmom,
+ * torque are n*3 doubles, q is n*4.  Syncs. */
+md_status md_get_state(md_system* s, double* x, double* v, double* f, double* q,
+                       double* angmom, double* torque);
+
+/* Half list of the last build in original ids, each pair as (min id, max id).
+ * Writes min(cap, |E|) pairs (2 int32 each) and stores |E| in *n_pairs.
+ * Syncs. */
+md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pairs);
+
+/* Counters; syncs. */
+md_status md_stats(md_system* s, md_stats_t* out);
+
+/* Destroy the handle (does not free the caller's buffers). */
+void md_destroy(md_system* s);
+
+/* Static description of a status code. */
+const char* md_status_str(int32_t status);
+
+/* Description of the last error on this handle ("" if none). */
+const char* md_last_error(const md_system* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBMD_H */

@@ -1,0 +1,515 @@
+// Host engine behind the C ABI of include/md.h: parameter validation, carving
+// of the caller's two device buffers, call ordering, and the per-step launch
+// sequence.  No device memory is allocated here; all work goes on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/md.h"
+#include "md_internal.h"
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr long long kSlack = 64;  // spare half-list entries
+
+struct Layout {
+    uint64_t state_bytes = 0, ws_bytes = 0;
+    // state offsets
+    uint64_t pos, vel, frc, quat, angm, trq, id;
+    // workspace offsets
+    uint64_t xbuild, tpos, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
+        ncount, hcount, hstart, hj, chunk_row, bsum, epart, wpart, kpart, red, ctrl;
+    int nc = 0, ncell = 0, nblk = 0;
+    long long max_half = 0;
+};
+
+uint64_t take(uint64_t& cur, uint64_t bytes) {
+    uint64_t off = cur;
+    cur += (bytes + kAlign - 1) / kAlign * kAlign;
+    return off;
+}
+
+md_status validate(const md_params* p) {
+    if (!p) return MD_ERR_INVALID_ARG;
+    auto fin = [](double v) { return std::isfinite(v); };
+    if (p->n < 2 || p->max_neighbors < 1) return MD_ERR_INVALID_ARG;
+    if (p->pot != MD_POT_LJ && p->pot != MD_POT_PATCHY) return MD_ERR_INVALID_ARG;
+    if (p->prec < MD_PREC_FP64 || p->prec > MD_PREC_FP32_KAHAN) return MD_ERR_INVALID_ARG;
+    if (!fin(p->box) || !(p->box > 0)) return MD_ERR_INVALID_ARG;
+    if (!fin(p->rcut) || !(p->rcut > 0)) return MD_ERR_INVALID_ARG;
+    if (!fin(p->skin) || !(p->skin >= 0)) return MD_ERR_INVALID_ARG;
+    if (!fin(p->dt) || !(p->dt > 0)) return MD_ERR_INVALID_ARG;
+    if (!fin(p->mass) || !(p->mass > 0)) return MD_ERR_INVALID_ARG;
+    if (!fin(p->eps) || !(p->eps >= 0) || !fin(p->sigma) || !(p->sigma > 0))
+        return MD_ERR_INVALID_ARG;
+    if (p->pot == MD_POT_PATCHY) {
+        if (!fin(p->patch_w) || !(p->patch_w > 0) || !fin(p->inertia) || !(p->inertia > 0) ||
+            !fin(p->patch_delta) || !(p->patch_delta >= 0) || !fin(p->eps_p) ||
+            !fin(p->patch_rcut))
+            return MD_ERR_INVALID_ARG;
+    }
+    double rv = p->rcut + p->skin;
+    if (!(p->box > 2.0 * rv)) return MD_ERR_BOX_TOO_SMALL;
+    // 32-bit slot and half-list indices
+    if ((long long)p->n * p->max_neighbors / 2 + kSlack > 2000000000LL)
+        return MD_ERR_INVALID_ARG;
+    return MD_OK;
+}
+
+}  // namespace
+
+namespace {
+
+Layout layout(const md_params& p) {
+    Layout L;
+    uint64_t n = (uint64_t)p.n;
+    double rv = p.rcut + p.skin;
+    int nc = (int)std::floor(p.box / (rv * (1.0 + 1e-10)));
+    nc = std::max(nc, 1);
+    while ((long long)nc * nc * nc > (1LL << 26)) nc--;
+    L.nc = nc;
+    L.ncell = nc * nc * nc;
+    L.nblk = (int)((n + md::kBlock - 1) / md::kBlock);
+    L.max_half = (long long)n * p.max_neighbors / 2 + kSlack;
+    bool patchy = p.pot == MD_POT_PATCHY;
+    uint64_t d4 = 32 * n;
+    uint64_t cur = 0;
+    L.pos = take(cur, d4);
+    L.vel = take(cur, d4);
+    L.frc = take(cur, d4);
+    L.quat = take(cur, patchy ? d4 : 0);
+    L.angm = take(cur, patchy ? d4 : 0);
+    L.trq = take(cur, patchy ? d4 : 0);
+    L.id = take(cur, 4 * n);
+    L.state_bytes = cur;
+    cur = 0;
+    L.ctrl = take(cur, sizeof(md::Ctrl));
+    L.xbuild = take(cur, d4);
+    L.tpos = take(cur, d4);
+    L.tvel = take(cur, d4);
+    L.tquat = take(cur, patchy ? d4 : 0);
+    L.tangm = take(cur, patchy ? d4 : 0);
+    L.tid = take(cur, 4 * n);
+    L.cell = take(cur, 4 * n);
+    L.rank = take(cur, 4 * n);
+    L.ccount = take(cur, 4 * (uint64_t)L.ncell);
+    L.cstart = take(cur, 4 * ((uint64_t)L.ncell + 1));
+    L.order = take(cur, 4 * n);
+    L.nbr = take(cur, 4 * n * (uint64_t)p.max_neighbors);
+    L.ncount = take(cur, 4 * n);
+    L.hcount = take(cur, 4 * n);
+    L.hstart = take(cur, 4 * (n + 1));
+    L.hj = take(cur, 4 * (uint64_t)L.max_half);
+    L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
+    L.bsum = take(cur, 4 * (uint64_t)L.nblk);
+    L.epart = take(cur, 8 * n);
+    L.wpart = take(cur, 8 * n);
+    L.kpart = take(cur, 8 * n);
+    L.red = take(cur, 8 * (3 * (uint64_t)md::kRedBlocks + 3));
+    L.ws_bytes = cur;
+    return L;
+}
+
+const char* status_text(int s) {
+    switch (s) {
+        case MD_OK: return "ok";
+        case MD_ERR_INVALID_ARG: return "invalid argument";
+        case MD_ERR_BUFFER_TOO_SMALL: return "buffer too small or misaligned";
+        case MD_ERR_HIP: return "HIP runtime error";
+        case MD_ERR_NEIGHBOR_OVERFLOW: return "Verlet list overflow (raise max_neighbors)";
+        case MD_ERR_BOX_TOO_SMALL: return "box must exceed 2 (rcut + skin)";
+        case MD_ERR_NONFINITE: return "non-finite force or position";
+        case MD_ERR_STATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+}  // namespace
+
+struct md_system {
+    md_params p;
+    Layout lay;
+    md::Sys sys;
+    hipStream_t stream;
+    bool state_set = false;
+    bool cells_pending = false;
+    bool lists_valid = false;
+    bool forces_valid = false;
+    long long steps = 0;
+    int edge_grid = 1;
+    std::string err;
+
+    md_status fail(md_status st, const std::string& msg) {
+        err = msg;
+        return st;
+    }
+    md_status hip(hipError_t e, const char* where) {
+        if (e == hipSuccess) return MD_OK;
+        err = std::string(where) + ": " + hipGetErrorString(e);
+        return MD_ERR_HIP;
+    }
+    // Waits for the stream and turns sticky device flags into a status.
+    md_status sync_check() {
+        md_status st = hip(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        if (st != MD_OK) return st;
+        md::Ctrl c;
+        st = hip(hipMemcpy(&c, sys.ctrl, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy(ctrl)");
+        if (st != MD_OK) return st;
+        if (c.overflow)
+            return fail(MD_ERR_NEIGHBOR_OVERFLOW,
+                        "a Verlet list exceeded max_neighbors=" + std::to_string(p.max_neighbors) +
+                            " (longest " + std::to_string(c.max_count) + ")");
+        if (c.nonfinite) return fail(MD_ERR_NONFINITE, "non-finite force");
+        return MD_OK;
+    }
+};
+
+extern "C" {
+
+md_status md_query_sizes(const md_params* p, md_sizes* out) {
+    if (!out) return MD_ERR_INVALID_ARG;
+    md_status st = validate(p);
+    if (st != MD_OK) return st;
+    Layout L = layout(*p);
+    out->state_bytes = L.state_bytes;
+    out->workspace_bytes = L.ws_bytes;
+    out->alignment = kAlign;
+    return MD_OK;
+}
+
+md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, void* d_workspace,
+                    uint64_t workspace_bytes, void* hip_stream, md_system** out) {
+    if (!out) return MD_ERR_INVALID_ARG;
+    *out = nullptr;
+    md_status st = validate(p);
+    if (st != MD_OK) return st;
+    if (!d_state || !d_workspace) return MD_ERR_INVALID_ARG;
+    Layout L = layout(*p);
+    if (state_bytes < L.state_bytes || workspace_bytes < L.ws_bytes) return MD_ERR_BUFFER_TOO_SMALL;
+    if ((uintptr_t)d_state % kAlign || (uintptr_t)d_workspace % kAlign)
+        return MD_ERR_BUFFER_TOO_SMALL;
+
+    md_system* s = new md_system();
+    s->p = *p;
+    s->lay = L;
+    s->stream = (hipStream_t)hip_stream;
+    md::Sys& y = s->sys;
+    std::memset(&y, 0, sizeof y);
+    char* S = (char*)d_state;
+    char* W = (char*)d_workspace;
+    bool patchy = p->pot == MD_POT_PATCHY;
+    y.n = p->n;
+    y.nc = L.nc;
+    y.ncell = L.ncell;
+    y.cap = p->max_neighbors;
+    y.pot = p->pot;
+    y.nblk = L.nblk;
+    y.max_half = L.max_half;
+    y.box = p->box;
+    y.inv_box = 1.0 / p->box;
+    y.cell_inv = L.nc / p->box;
+    double rv = p->rcut + p->skin;
+    y.rv2 = rv * rv;
+    y.rc2 = p->rcut * p->rcut;
+    y.disp2 = 0.25 * p->skin * p->skin;
+    y.dt = p->dt;
+    y.hdt = 0.5 * p->dt;
+    y.inv_mass = 1.0 / p->mass;
+    y.inv_inertia = patchy ? 1.0 / p->inertia : 0.0;
+    md::set_potential(y, p->eps, p->sigma, p->rcut, p->eps_p, patchy ? p->patch_w : 1.0,
+                      p->patch_delta, p->patch_rcut);
+    y.pos = (double4*)(S + L.pos);
+    y.vel = (double4*)(S + L.vel);
+    y.frc = (double4*)(S + L.frc);
+    y.quat = patchy ? (double4*)(S + L.quat) : nullptr;
+    y.angm = patchy ? (double4*)(S + L.angm) : nullptr;
+    y.trq = patchy ? (double4*)(S + L.trq) : nullptr;
+    y.id = (int*)(S + L.id);
+    y.ctrl = (md::Ctrl*)(W + L.ctrl);
+    y.xbuild = (double4*)(W + L.xbuild);
+    y.tpos = (double4*)(W + L.tpos);
+    y.tvel = (double4*)(W + L.tvel);
+    y.tquat = patchy ? (double4*)(W + L.tquat) : nullptr;
+    y.tangm = patchy ? (double4*)(W + L.tangm) : nullptr;
+    y.tid = (int*)(W + L.tid);
+    y.cell = (int*)(W + L.cell);
+    y.rank = (int*)(W + L.rank);
+    y.ccount = (int*)(W + L.ccount);
+    y.cstart = (int*)(W + L.cstart);
+    y.order = (int*)(W + L.order);
+    y.nbr = (int*)(W + L.nbr);
+    y.ncount = (int*)(W + L.ncount);
+    y.hcount = (int*)(W + L.hcount);
+    y.hstart = (int*)(W + L.hstart);
+    y.hj = (int*)(W + L.hj);
+    y.chunk_row = (int*)(W + L.chunk_row);
+    y.bsum = (int*)(W + L.bsum);
+    y.epart = (double*)(W + L.epart);
+    y.wpart = (double*)(W + L.wpart);
+    y.kpart = (double*)(W + L.kpart);
+    y.red = (double*)(W + L.red);
+
+    long long waves = (L.max_half + md::kWave - 1) / md::kWave;
+    long long blocks = (waves + 3) / 4;
+    s->edge_grid = (int)std::max(1LL, std::min(blocks, 4096LL));
+
+    // One-time clears at creation (never inside a captured step).
+    st = s->hip(hipMemsetAsync(y.ccount, 0, 4 * (size_t)L.ncell, s->stream), "clear cell counts");
+    if (st == MD_OK) st = s->hip(hipMemsetAsync(d_state, 0, L.state_bytes, s->stream), "clear state");
+    if (st == MD_OK) st = s->hip(md::launch_clear_ctrl(y, s->stream), "clear control");
+    if (st == MD_OK) st = s->hip(hipStreamSynchronize(s->stream), "create sync");
+    if (st != MD_OK) {
+        delete s;
+        return st;
+    }
+    *out = s;
+    return MD_OK;
+}
+
+md_status md_set_state(md_system* s, const double* x, const double* v, const double* q,
+                       const double* angmom) {
+    if (!s || !x || !v) return MD_ERR_INVALID_ARG;
+    bool patchy = s->p.pot == MD_POT_PATCHY;
+    if (patchy && (!q || !angmom)) return s->fail(MD_ERR_INVALID_ARG, "patchy needs q and angmom");
+    int n = s->p.n;
+    double L = s->p.box;
+    std::vector<double4> hp(n), hv(n), hq, hl;
+    std::vector<int> hid(n);
+    for (int i = 0; i < n; i++) {
+        double c[3];
+        for (int k = 0; k < 3; k++) {
+            double y = x[3 * i + k];
+            if (!std::isfinite(y) || !std::isfinite(v[3 * i + k]))
+                return s->fail(MD_ERR_NONFINITE, "non-finite input state");
+            y -= L * std::floor(y / L);
+            if (y >= L) y -= L;
+            if (y < 0) y += L;
+            c[k] = y;
+        }
+        hp[i] = make_double4(c[0], c[1], c[2], 0.0);
+        hv[i] = make_double4(v[3 * i], v[3 * i + 1], v[3 * i + 2], 0.0);
+        hid[i] = i;
+    }
+    if (patchy) {
+        hq.resize(n);
+        hl.resize(n);
+        for (int i = 0; i < n; i++) {
+            const double* a = q + 4 * i;
+            double nn = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+            if (!(nn > 0) || !std::isfinite(nn))
+                return s->fail(MD_ERR_INVALID_ARG, "quaternion must be non-zero");
+            hq[i] = make_double4(a[0] / nn, a[1] / nn, a[2] / nn, a[3] / nn);
+            hl[i] = make_double4(angmom[3 * i], angmom[3 * i + 1], angmom[3 * i + 2], 0.0);
+        }
+    }
+    md::Sys& y = s->sys;
+    hipStream_t st = s->stream;
+    size_t b4 = sizeof(double4) * (size_t)n;
+    md_status r = s->hip(hipMemcpyAsync(y.pos, hp.data(), b4, hipMemcpyHostToDevice, st), "upload x");
+    if (r == MD_OK) r = s->hip(hipMemcpyAsync(y.vel, hv.data(), b4, hipMemcpyHostToDevice, st), "upload v");
+    if (r == MD_OK) r = s->hip(hipMemcpyAsync(y.id, hid.data(), 4 * (size_t)n, hipMemcpyHostToDevice, st), "upload id");
+    if (r == MD_OK) r = s->hip(hipMemsetAsync(y.frc, 0, b4, st), "clear F");
+    if (patchy) {
+        if (r == MD_OK) r = s->hip(hipMemcpyAsync(y.quat, hq.data(), b4, hipMemcpyHostToDevice, st), "upload q");
+        if (r == MD_OK) r = s->hip(hipMemcpyAsync(y.angm, hl.data(), b4, hipMemcpyHostToDevice, st), "upload L");
+        if (r == MD_OK) r = s->hip(hipMemsetAsync(y.trq, 0, b4, st), "clear tau");
+    }
+    if (r == MD_OK) r = s->hip(md::launch_clear_ctrl(y, st), "clear control");
+    if (r == MD_OK) r = s->hip(hipStreamSynchronize(st), "set_state sync");
+    if (r != MD_OK) return r;
+    s->state_set = true;
+    s->cells_pending = false;
+    s->lists_valid = false;
+    s->forces_valid = false;
+    s->err.clear();
+    return MD_OK;
+}
+
+md_status md_build_cells(md_system* s) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    if (!s->state_set) return s->fail(MD_ERR_STATE, "md_set_state first");
+    md_status r = s->hip(md::launch_set_rebuild(s->sys, s->stream), "set rebuild");
+    if (r == MD_OK) r = s->hip(md::launch_rebuild(s->sys, s->stream, true, false), "cell sort");
+    if (r != MD_OK) return r;
+    s->cells_pending = true;
+    s->lists_valid = false;
+    s->forces_valid = false;
+    return MD_OK;
+}
+
+md_status md_build_neighbors(md_system* s) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    if (!s->cells_pending) return s->fail(MD_ERR_STATE, "md_build_cells first");
+    md_status r = s->hip(md::launch_rebuild(s->sys, s->stream, false, true), "list build");
+    if (r == MD_OK) r = s->hip(md::launch_clear_rebuild(s->sys, s->stream), "clear rebuild");
+    if (r != MD_OK) return r;
+    s->cells_pending = false;
+    s->lists_valid = true;
+    s->forces_valid = false;
+    return MD_OK;
+}
+
+md_status md_forces(md_system* s, int32_t mode) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    if (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE) return s->fail(MD_ERR_INVALID_ARG, "mode");
+    if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
+    md_status r = s->hip(md::launch_forces(s->sys, mode, s->p.prec, false, s->stream, s->edge_grid),
+                         "forces");
+    if (r != MD_OK) return r;
+    s->forces_valid = true;
+    return MD_OK;
+}
+
+md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    if (nsteps < 0 || (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE))
+        return s->fail(MD_ERR_INVALID_ARG, "nsteps/mode");
+    if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
+    if (!s->forces_valid) {
+        md_status r = md_forces(s, mode);
+        if (r != MD_OK) return r;
+    }
+    const md::Sys& y = s->sys;
+    bool edge = mode == MD_MODE_EDGE;
+    for (int k = 0; k < nsteps; k++) {
+        hipError_t e = md::launch_kick_drift(y, edge, s->stream);
+        if (e == hipSuccess) e = md::launch_rebuild(y, s->stream, true, true);
+        if (e == hipSuccess) e = md::launch_forces(y, mode, s->p.prec, true, s->stream, s->edge_grid);
+        if (e != hipSuccess) return s->hip(e, "step launch");
+    }
+    s->steps += nsteps;
+    return s->sync_check();
+}
+
+md_status md_energy(md_system* s, double* e_kin, double* e_pot, double* virial) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
+    md_status r = s->hip(md::launch_energy(s->sys, s->p.prec, s->stream), "energy");
+    if (r != MD_OK) return r;
+    double h[3];
+    r = s->hip(hipMemcpyAsync(h, s->sys.red + 3 * md::kRedBlocks, sizeof h, hipMemcpyDeviceToHost,
+                              s->stream),
+               "energy download");
+    if (r == MD_OK) r = s->sync_check();
+    if (r != MD_OK) return r;
+    if (e_kin) *e_kin = h[0];
+    if (e_pot) *e_pot = h[1];
+    if (virial) *virial = h[2];
+    return MD_OK;
+}
+
+static md_status download_ids(md_system* s, std::vector<int>& id) {
+    id.resize(s->p.n);
+    return s->hip(hipMemcpyAsync(id.data(), s->sys.id, 4 * (size_t)s->p.n, hipMemcpyDeviceToHost,
+                                 s->stream),
+                  "download ids");
+}
+
+md_status md_particle_energies(md_system* s, double* e) {
+    if (!s || !e) return MD_ERR_INVALID_ARG;
+    if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
+    int n = s->p.n;
+    std::vector<double> h(n);
+    std::vector<int> id;
+    md_status r = s->hip(md::launch_energy(s->sys, s->p.prec, s->stream), "energy");
+    if (r == MD_OK)
+        r = s->hip(hipMemcpyAsync(h.data(), s->sys.epart, 8 * (size_t)n, hipMemcpyDeviceToHost,
+                                  s->stream),
+                   "download e");
+    if (r == MD_OK) r = download_ids(s, id);
+    if (r == MD_OK) r = s->sync_check();
+    if (r != MD_OK) return r;
+    for (int k = 0; k < n; k++) e[id[k]] = h[k];
+    return MD_OK;
+}
+
+md_status md_get_state(md_system* s, double* x, double* v, double* f, double* q, double* angmom,
+                       double* torque) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    if (!s->state_set) return s->fail(MD_ERR_STATE, "md_set_state first");
+    bool patchy = s->p.pot == MD_POT_PATCHY;
+    if (!patchy && (q || angmom || torque)) return s->fail(MD_ERR_INVALID_ARG, "LJ has no rotation");
+    int n = s->p.n;
+    std::vector<int> id;
+    md_status r = download_ids(s, id);
+    struct Item {
+        double* dst;
+        double4* src;
+        int width;
+    } items[6] = {{x, s->sys.pos, 3},     {v, s->sys.vel, 3},    {f, s->sys.frc, 3},
+                  {q, s->sys.quat, 4},    {angmom, s->sys.angm, 3}, {torque, s->sys.trq, 3}};
+    std::vector<double4> buf(n);
+    if (r == MD_OK) r = s->hip(hipStreamSynchronize(s->stream), "get_state sync");
+    for (auto& it : items) {
+        if (r != MD_OK || !it.dst) continue;
+        r = s->hip(hipMemcpy(buf.data(), it.src, sizeof(double4) * (size_t)n, hipMemcpyDeviceToHost),
+                   "download state");
+        if (r != MD_OK) break;
+        for (int k = 0; k < n; k++) {
+            double* d = it.dst + (size_t)it.width * id[k];
+            d[0] = buf[k].x;
+            d[1] = buf[k].y;
+            d[2] = buf[k].z;
+            if (it.width == 4) d[3] = buf[k].w;
+        }
+    }
+    if (r != MD_OK) return r;
+    return s->sync_check();
+}
+
+md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pairs) {
+    if (!s || !n_pairs || cap < 0 || (cap > 0 && !pairs)) return MD_ERR_INVALID_ARG;
+    if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
+    md_status r = s->sync_check();
+    if (r != MD_OK) return r;
+    md::Ctrl c;
+    r = s->hip(hipMemcpy(&c, s->sys.ctrl, sizeof c, hipMemcpyDeviceToHost), "ctrl");
+    if (r != MD_OK) return r;
+    int n = s->p.n;
+    std::vector<int> id(n), hs(n + 1), hj((size_t)c.npairs);
+    r = s->hip(hipMemcpy(id.data(), s->sys.id, 4 * (size_t)n, hipMemcpyDeviceToHost), "ids");
+    if (r == MD_OK)
+        r = s->hip(hipMemcpy(hs.data(), s->sys.hstart, 4 * (size_t)(n + 1), hipMemcpyDeviceToHost),
+                   "hstart");
+    if (r == MD_OK && c.npairs > 0)
+        r = s->hip(hipMemcpy(hj.data(), s->sys.hj, 4 * (size_t)c.npairs, hipMemcpyDeviceToHost), "hj");
+    if (r != MD_OK) return r;
+    *n_pairs = c.npairs;
+    int64_t w = 0;
+    for (int i = 0; i < n && w < cap; i++)
+        for (int k = hs[i]; k < hs[i + 1] && w < cap; k++) {
+            int a = id[i], b = id[hj[k]];
+            pairs[2 * w] = std::min(a, b);
+            pairs[2 * w + 1] = std::max(a, b);
+            w++;
+        }
+    return MD_OK;
+}
+
+md_status md_stats(md_system* s, md_stats_t* out) {
+    if (!s || !out) return MD_ERR_INVALID_ARG;
+    md_status r = s->hip(hipStreamSynchronize(s->stream), "stats sync");
+    md::Ctrl c;
+    if (r == MD_OK) r = s->hip(hipMemcpy(&c, s->sys.ctrl, sizeof c, hipMemcpyDeviceToHost), "ctrl");
+    if (r != MD_OK) return r;
+    out->steps = s->steps;
+    out->rebuilds = c.rebuilds;
+    out->pairs = c.npairs;
+    out->max_list_len = c.max_count;
+    out->n_cells = s->lay.nc;
+    return MD_OK;
+}
+
+void md_destroy(md_system* s) { delete s; }
+
+const char* md_status_str(int32_t status) { return status_text(status); }
+
+const char* md_last_error(const md_system* s) { return s ? s->err.c_str() : ""; }
+
+}  // extern "C"

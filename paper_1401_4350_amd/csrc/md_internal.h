@@ -1,0 +1,110 @@
+// Internal types shared by the HIP kernels (md_kernels.hip) and the host
+// engine (md_engine.hip).  Not part of the public ABI (include/md.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace md {
+
+constexpr int kBlock = 256;  // threads per block of the per-particle kernels
+constexpr int kWave = 64;    // CDNA wavefront
+constexpr int kScanThreads = 1024;
+
+// Device-resident control block (one per system).  Written by kernels, read by
+// the host only at syncing calls.
+struct Ctrl {
+    int rebuild;        // set when a list rebuild is due; cleared by the force pass
+    int overflow;       // sticky: a list exceeded its capacity
+    int nonfinite;      // sticky: a force or position was NaN/Inf
+    int max_count;      // longest full list at the last build
+    long long npairs;   // half-list entries at the last build (clamped to capacity)
+    long long rebuilds; // number of builds
+    long long pad[4];
+};
+
+// Pair-potential constants in the arithmetic type of the pair maths.
+template <typename R>
+struct LJc {
+    R sig2, eps4, eps24, rc2, vshift;
+};
+
+template <typename R>
+struct PatchyC {
+    R sig2, eps4, eps24, eps, wca2;  // WCA core
+    R eps_p, inv_w2, delta, rpc2;    // patches (rpc2 <= 0: no patch cut-off)
+};
+
+// Everything a kernel needs, passed by value.  Particle arrays are packed
+// 32-byte records (x, y, z, unused) in cell-sorted slot order.
+struct Sys {
+    int n;          // particles
+    int nc;         // cells per side
+    int ncell;      // nc^3
+    int cap;        // full-list capacity per particle
+    int pot;        // 0 LJ, 1 patchy
+    int nblk;       // ceil(n / kBlock)
+    long long max_half;  // half-list capacity (entries)
+    double box, inv_box, cell_inv;  // L, 1/L, nc/L
+    double rv2;     // (r_c + r_s)^2
+    double rc2;     // r_c^2
+    double disp2;   // (r_s/2)^2
+    double dt, hdt, inv_mass, inv_inertia;
+    LJc<double> l64;
+    LJc<float> l32;
+    PatchyC<double> p64;
+    PatchyC<float> p32;
+
+    // state (caller's state buffer)
+    double4* pos;
+    double4* vel;
+    double4* frc;
+    double4* quat;   // patchy: (w, x, y, z)
+    double4* angm;   // patchy: angular momentum (space frame)
+    double4* trq;    // patchy: torque
+    int* id;         // slot -> original id
+
+    // workspace
+    double4* xbuild;
+    double4* tpos;
+    double4* tvel;
+    double4* tquat;
+    double4* tangm;
+    int* tid;
+    int* cell;
+    int* rank;
+    int* ccount;
+    int* cstart;     // ncell + 1
+    int* order;
+    int* nbr;        // ELL: nbr[k * n + i], k < cap
+    int* ncount;
+    int* hcount;
+    int* hstart;     // n + 1
+    int* hj;         // half-list partner slots, CSR by row
+    int* chunk_row;  // first row of every 64-pair chunk of the half list
+    int* bsum;       // per-block half counts, then offsets
+    double* epart;   // per-particle potential energy
+    double* wpart;   // per-particle virial
+    double* kpart;   // per-particle kinetic energy
+    double* red;     // reduction partials (3 * kRedBlocks) + result (3)
+    Ctrl* ctrl;
+};
+
+constexpr int kRedBlocks = 1024;
+
+// Host-side launchers (md_kernels.hip).  All enqueue on `st`.
+hipError_t launch_set_rebuild(const Sys& s, hipStream_t st);
+hipError_t launch_clear_ctrl(const Sys& s, hipStream_t st);
+hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists);
+hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_t st,
+                         int edge_grid);
+hipError_t launch_kick_drift(const Sys& s, bool zero_forces, hipStream_t st);
+hipError_t launch_kick(const Sys& s, hipStream_t st);
+hipError_t launch_energy(const Sys& s, int prec, hipStream_t st);
+hipError_t launch_clear_rebuild(const Sys& s, hipStream_t st);
+
+// Fills the potential constants of s from the physical parameters.
+void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, double w,
+                   double delta, double rpc);
+
+}  // namespace md

@@ -1,0 +1,222 @@
+"""Thin ctypes binding of libmd.so (include/md.h).
+
+Argument marshalling only: every step of the force path runs in the HIP
+kernels behind the C ABI.  PyTorch provides the two device buffers and the
+stream.  Importing this module loads libmd.so and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1401_4350_amd.build` "
+        "(the engine has no fallback path)")
+
+# torch first: libmd.so then binds to the HIP runtime torch has already loaded
+_lib = ctypes.CDLL(LIB_PATH)
+
+MD_OK = 0
+MODE = {"vertex": 0, "edge": 1}
+POT = {"lj": 0, "patchy": 1}
+PREC = {"fp64": 0, "fp32": 1, "fp32_kahan": 2}
+
+
+class MDParams(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("pot", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("max_neighbors", ctypes.c_int32), ("box", ctypes.c_double),
+                ("eps", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("rcut", ctypes.c_double), ("skin", ctypes.c_double),
+                ("mass", ctypes.c_double), ("dt", ctypes.c_double),
+                ("eps_p", ctypes.c_double), ("patch_w", ctypes.c_double),
+                ("patch_delta", ctypes.c_double), ("patch_rcut", ctypes.c_double),
+                ("inertia", ctypes.c_double)]
+
+
+class MDSizes(ctypes.Structure):
+    _fields_ = [("state_bytes", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64),
+                ("alignment", ctypes.c_uint64)]
+
+
+class MDStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
+                ("pairs", ctypes.c_int64), ("max_list_len", ctypes.c_int32),
+                ("n_cells", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_sys_p = ctypes.c_void_p
+
+_SIGS = {
+    "md_query_sizes": ([ctypes.POINTER(MDParams), ctypes.POINTER(MDSizes)], ctypes.c_int),
+    "md_create": ([ctypes.POINTER(MDParams), _P, ctypes.c_uint64, _P, ctypes.c_uint64, _P,
+                   ctypes.POINTER(_sys_p)], ctypes.c_int),
+    "md_set_state": ([_sys_p, _D, _D, _D, _D], ctypes.c_int),
+    "md_build_cells": ([_sys_p], ctypes.c_int),
+    "md_build_neighbors": ([_sys_p], ctypes.c_int),
+    "md_forces": ([_sys_p, ctypes.c_int32], ctypes.c_int),
+    "md_step": ([_sys_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "md_energy": ([_sys_p, _D, _D, _D], ctypes.c_int),
+    "md_particle_energies": ([_sys_p, _D], ctypes.c_int),
+    "md_get_state": ([_sys_p, _D, _D, _D, _D, _D, _D], ctypes.c_int),
+    "md_get_pairs": ([_sys_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
+                      ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "md_stats": ([_sys_p, ctypes.POINTER(MDStats)], ctypes.c_int),
+    "md_destroy": ([_sys_p], None),
+    "md_status_str": ([ctypes.c_int32], ctypes.c_char_p),
+    "md_last_error": ([_sys_p], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class MDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.md_status_str(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(_D)
+
+
+def make_params(w, prec: str = "fp64") -> MDParams:
+    """md_params from a Workload of paper_1401_4350_amd.inputs."""
+    p = MDParams()
+    p.n, p.pot, p.prec = w.n, POT[w.pot], PREC[prec]
+    p.max_neighbors = w.list_capacity()
+    p.box, p.eps, p.sigma, p.rcut, p.skin = w.box, w.eps, w.sigma, w.rcut, w.skin
+    p.mass, p.dt = w.mass, w.dt
+    p.eps_p, p.patch_w, p.patch_delta = w.eps_p, w.patch_w, w.patch_delta
+    p.patch_rcut, p.inertia = w.patch_rcut, w.inertia
+    return p
+
+
+def query_sizes(p: MDParams) -> MDSizes:
+    s = MDSizes()
+    st = _lib.md_query_sizes(ctypes.byref(p), ctypes.byref(s))
+    if st != MD_OK:
+        raise MDError(st, "md_query_sizes")
+    return s
+
+
+class System:
+    """One simulated system on the current HIP device (see include/md.h)."""
+
+    def __init__(self, params: MDParams, stream: torch.cuda.Stream | None = None):
+        self.params = params
+        self.n = params.n
+        self.patchy = params.pot == POT["patchy"]
+        sz = query_sizes(params)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        a = int(sz.alignment)
+        # over-allocate by one alignment unit and align the base pointer
+        self._state = torch.empty(int(sz.state_bytes) + a, dtype=torch.uint8, device=dev)
+        self._ws = torch.empty(int(sz.workspace_bytes) + a, dtype=torch.uint8, device=dev)
+        sp = (self._state.data_ptr() + a - 1) // a * a
+        wp = (self._ws.data_ptr() + a - 1) // a * a
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _sys_p()
+        st = _lib.md_create(ctypes.byref(params), sp, sz.state_bytes, wp, sz.workspace_bytes,
+                            self.stream.cuda_stream, ctypes.byref(h))
+        if st != MD_OK:
+            raise MDError(st, "md_create")
+        self._h = h
+        self.state_bytes = int(sz.state_bytes)
+        self.workspace_bytes = int(sz.workspace_bytes)
+
+    def _check(self, st, what):
+        if st != MD_OK:
+            raise MDError(st, f"{what}: {_lib.md_last_error(self._h).decode()}")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.md_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls ---------------------------------------------------------------
+    def set_state(self, x, v, q=None, angmom=None):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(self.n, 3)
+        v = np.ascontiguousarray(v, dtype=np.float64).reshape(self.n, 3)
+        if self.patchy:
+            q = np.ascontiguousarray(q, dtype=np.float64).reshape(self.n, 4)
+            angmom = np.ascontiguousarray(angmom, dtype=np.float64).reshape(self.n, 3)
+        else:
+            q = angmom = None
+        self._check(_lib.md_set_state(self._h, _dp(x), _dp(v), _dp(q), _dp(angmom)),
+                    "md_set_state")
+
+    def build_cells(self):
+        self._check(_lib.md_build_cells(self._h), "md_build_cells")
+
+    def build_neighbors(self):
+        self._check(_lib.md_build_neighbors(self._h), "md_build_neighbors")
+
+    def build(self):
+        self.build_cells()
+        self.build_neighbors()
+
+    def forces(self, mode: str = "vertex"):
+        self._check(_lib.md_forces(self._h, MODE[mode]), "md_forces")
+
+    def step(self, nsteps: int, mode: str = "vertex"):
+        self._check(_lib.md_step(self._h, nsteps, MODE[mode]), "md_step")
+
+    def energy(self):
+        k, p, w = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(_lib.md_energy(self._h, ctypes.byref(k), ctypes.byref(p), ctypes.byref(w)),
+                    "md_energy")
+        return k.value, p.value, w.value
+
+    def particle_energies(self):
+        e = np.zeros(self.n)
+        self._check(_lib.md_particle_energies(self._h, _dp(e)), "md_particle_energies")
+        return e
+
+    def get_state(self):
+        n = self.n
+        out = {k: np.zeros((n, 3)) for k in ("x", "v", "f")}
+        if self.patchy:
+            out["q"] = np.zeros((n, 4))
+            out["angmom"] = np.zeros((n, 3))
+            out["torque"] = np.zeros((n, 3))
+        self._check(_lib.md_get_state(self._h, _dp(out["x"]), _dp(out["v"]), _dp(out["f"]),
+                                      _dp(out.get("q")), _dp(out.get("angmom")),
+                                      _dp(out.get("torque"))), "md_get_state")
+        return out
+
+    def pairs(self):
+        """Half list in original ids, sorted, as an (|E|, 2) int32 array."""
+        cnt = ctypes.c_int64()
+        self._check(_lib.md_get_pairs(self._h, None, 0, ctypes.byref(cnt)), "md_get_pairs")
+        out = np.zeros((max(cnt.value, 1), 2), dtype=np.int32)
+        self._check(_lib.md_get_pairs(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      cnt.value, ctypes.byref(cnt)), "md_get_pairs")
+        out = out[:cnt.value]
+        return out[np.lexsort((out[:, 1], out[:, 0]))]
+
+    def stats(self) -> dict:
+        s = MDStats()
+        self._check(_lib.md_stats(self._h, ctypes.byref(s)), "md_stats")
+        return dict(steps=s.steps, rebuilds=s.rebuilds, pairs=s.pairs,
+                    max_list_len=s.max_list_len, n_cells=s.n_cells)
+
+
+def lib():
+    return _lib

@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports every entry point include/md.h declares,
+and rejects bad parameters on the host before any HIP call (no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "md.h")
+
+
+@pytest.fixture(scope="module")
+def md():
+    from paper_1401_4350_amd import build
+    if not os.path.exists(build.LIB):
+        build.build()
+    from paper_1401_4350_amd import md as m
+    return m
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(md_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("md_create", "md_build_cells", "md_build_neighbors", "md_forces",
+                     "md_step", "md_energy", "md_query_sizes", "md_get_state", "md_destroy"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(md):
+    lib = md.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _params(md, **kw):
+    from paper_1401_4350_amd.inputs import WORKLOADS
+    p = md.make_params(WORKLOADS["lj_small"])
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_query_sizes(md):
+    s = md.query_sizes(_params(md))
+    assert s.alignment == 256
+    assert s.state_bytes >= 4096 * 3 * 32
+    # workspace holds at least the full lists
+    assert s.workspace_bytes >= 4096 * 4 * _params(md).max_neighbors
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n", 1, -1), ("box", 5.0, -5), ("dt", 0.0, -1), ("skin", -0.1, -1),
+    ("rcut", 0.0, -1), ("max_neighbors", 0, -1), ("mass", -1.0, -1), ("pot", 7, -1),
+    ("prec", 9, -1), ("box", float("nan"), -1),
+])
+def test_invalid_params_rejected_on_host(md, field, value, status):
+    p = _params(md, **{field: value})
+    s = md.MDSizes()
+    assert md.lib().md_query_sizes(ctypes.byref(p), ctypes.byref(s)) == status
+    h = ctypes.c_void_p()
+    # buffers are never touched: validation happens before any HIP call
+    assert md.lib().md_create(ctypes.byref(p), 256, 1 << 40, 512, 1 << 40, None,
+                              ctypes.byref(h)) == status
+    assert not h.value
+
+
+def test_buffer_checks_before_hip(md):
+    p = _params(md)
+    s = md.query_sizes(p)
+    h = ctypes.c_void_p()
+    lib = md.lib()
+    assert lib.md_create(ctypes.byref(p), 256, s.state_bytes - 1, 512, s.workspace_bytes,
+                         None, ctypes.byref(h)) == -2
+    assert lib.md_create(ctypes.byref(p), 257, s.state_bytes, 512, s.workspace_bytes,
+                         None, ctypes.byref(h)) == -2
+    assert lib.md_create(ctypes.byref(p), None, s.state_bytes, 512, s.workspace_bytes,
+                         None, ctypes.byref(h)) == -1
+
+
+def test_null_handle_calls(md):
+    lib = md.lib()
+    for name in ("md_build_cells", "md_build_neighbors"):
+        assert getattr(lib, name)(None) == -1
+    assert lib.md_forces(None, 0) == -1
+    assert lib.md_step(None, 1, 0) == -1
+    assert lib.md_status_str(-4).decode().startswith("Verlet list overflow")
+    assert lib.md_last_error(None).decode() == ""
