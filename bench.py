@@ -1,0 +1,191 @@
+#!/usr/bin/env python3
+"""Benchmark of the pair-force MD step on one MI355X.
+
+Workload (default): Lennard-Jones fluid, N = 262144, rho = 0.8, r_c = 2.5,
+skin 0.3, dt = 0.001, T = 1.5, FP64.  One timed step is one velocity-Verlet MD
+step: half kick + drift + rebuild test, the cell sort and list build when due
+(on the device), the force pass and the closing half kick.  The headline value
+is pair-force evaluations per second of the vertex decomposition, counting
+|E| (half-list entries, the edge method's thread count) per force pass; the
+edge decomposition and the FP32-force variants are timed the same way and
+reported beside it.
+
+Prints one JSON line.  Inputs are resident in HBM before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def vertex_step_bytes(n: int, pairs: int) -> int:
+    """Algorithmic bytes of one fused vertex force + half-kick launch (FP64):
+    every full-list entry read once (4 B, 2|E| entries), per particle the list
+    length (4 B), its own position (24 B), the force written (24 B) and the
+    velocity read and written (48 B).  Neighbour positions are gathers that the
+    method assumes are cache hits."""
+    return 8 * pairs + 100 * n
+
+
+def edge_pass_bytes(n: int, pairs: int) -> int:
+    """Algorithmic bytes of one edge force pass + kick: every half-list entry
+    (4 B), per particle the row start (4 B), its own position (24 B), forces
+    written (24 B) and read back by the kick (24 B), velocity read and written
+    (48 B).  Atomic read-modify-write traffic is not counted here."""
+    return 4 * pairs + 124 * n
+
+
+def time_mode(md, torch, w, state, mode, prec, steps, warmup):
+    g = md.System(md.make_params(w, prec))
+    g.set_state(state.x, state.v, state.q, state.angmom)
+    g.build()
+    g.forces(mode)
+    if warmup:
+        g.step(warmup, mode)
+    g.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(steps, mode)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = g.profile_read()
+    st = g.stats()
+    ke, pe, _ = g.energy()
+    g.close()
+    wall = t1 - t0
+    return dict(mode=mode, prec=prec, wall_s=wall, ms_per_step=1e3 * wall / steps,
+                pairs=int(st["pairs"]), rebuilds_total=int(st["rebuilds"]),
+                force_ms_per_step=prof["force_ms"] / steps,
+                integrate_ms_per_step=prof["integrate_ms"] / steps,
+                rebuild_ms_per_step=prof["rebuild_ms"] / steps,
+                energy_per_particle=(ke + pe) / w.n)
+
+
+def cpu_baseline(w, state, pairs, budget_s=20.0):
+    """The FP64 oracle (single-threaded C) on the same state: a few velocity-
+    Verlet steps, scaled to pair evaluations per second."""
+    import oracle
+    lj = oracle.LJ(w.eps, w.sigma, w.rcut)
+    t0 = time.perf_counter()
+    oracle.run(state.x, state.v, state.box, pot="lj", nsteps=1, dt=w.dt, skin=w.skin, lj=lj)
+    t1 = time.perf_counter() - t0          # two force evaluations
+    k = max(1, min(60, int(budget_s / max(t1 / 2, 1e-6)) - 1))
+    t0 = time.perf_counter()
+    oracle.run(state.x, state.v, state.box, pot="lj", nsteps=k, dt=w.dt, skin=w.skin, lj=lj)
+    dt = time.perf_counter() - t0
+    calls = k + 1                           # initial force + one per step
+    return {"value": pairs * calls / dt, "unit": "pair evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle velocity Verlet, {k} steps ({calls} force passes) of the same "
+                      f"N={w.n} state, {dt:.1f} s single-threaded",
+            "steps_per_s": k / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="lj_many")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "fp32_kahan"])
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="time only the headline (vertex) and edge modes")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (for counter scaling)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this engine runs one system per GPU on a single GPU; "
+                                   "--gpus must be 1 (multi-GPU sharding is a design note "
+                                   "only)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1401_4350_amd import md
+    from paper_1401_4350_amd.inputs import WORKLOADS, make_state
+
+    torch.cuda.set_device(0)
+    w = WORKLOADS[args.workload]
+    state = make_state(w, args.seed)
+
+    if args.calibrate_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    runs = {}
+    for mode in ("vertex", "edge"):
+        runs[mode] = time_mode(md, torch, w, state, mode, args.prec, args.steps, args.warmup)
+    variants = {}
+    if not args.no_variants and args.prec == "fp64":
+        for mode in ("vertex", "edge"):
+            variants[f"{mode}_fp32"] = time_mode(md, torch, w, state, mode, "fp32",
+                                                 args.steps, args.warmup)
+
+    head = runs["vertex"]
+    pairs = head["pairs"]
+    value = pairs / (head["ms_per_step"] * 1e-3)
+    nb = vertex_step_bytes(w.n, pairs)
+    t_kernel = head["force_ms_per_step"] * 1e-3
+    achieved = nb / t_kernel / 1e9
+
+    def summary(r, nbytes):
+        return {"ms_per_step": r["ms_per_step"], "md_steps_per_s": 1e3 / r["ms_per_step"],
+                "pair_evals_per_s": r["pairs"] / (r["ms_per_step"] * 1e-3),
+                "force_pass_us": 1e3 * r["force_ms_per_step"],
+                "integrate_us": 1e3 * r["integrate_ms_per_step"],
+                "rebuild_us_amortised": 1e3 * r["rebuild_ms_per_step"],
+                "force_pass_GBps": nbytes / (r["force_ms_per_step"] * 1e-3) / 1e9,
+                "pairs": r["pairs"], "list_builds": r["rebuilds_total"],
+                "energy_per_particle": r["energy_per_particle"]}
+
+    modes = {"vertex": summary(runs["vertex"], vertex_step_bytes(w.n, runs["vertex"]["pairs"])),
+             "edge": summary(runs["edge"], edge_pass_bytes(w.n, runs["edge"]["pairs"]))}
+    for k, r in variants.items():
+        nbv = (vertex_step_bytes if k.startswith("vertex") else edge_pass_bytes)(w.n, r["pairs"])
+        modes[k] = summary(r, nbv)
+    modes["edge_over_vertex_speedup"] = runs["vertex"]["ms_per_step"] / runs["edge"]["ms_per_step"]
+
+    out = {
+        "metric": "pair-force evals/s (LJ MD step, vertex decomposition)",
+        "value": value,
+        "unit": "pair evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "md_steps_per_s": 1e3 / head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32 pair maths, f64 sums and integration",
+        "data": "synthetic",
+        "config": {"workload": w.name, "pot": w.pot, "n": w.n, "rho": w.rho, "temp": w.temp,
+                   "rcut": w.rcut, "skin": w.skin, "dt": w.dt, "prec": args.prec,
+                   "max_neighbors": w.list_capacity(), "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_vertex_lj<FP64, fused kick>",
+                     "bytes_per_launch": nb, "avg_launch_us": t_kernel * 1e6},
+        "modes": modes,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, state, pairs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,25 @@ md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pai
 /* Counters; syncs. */
 md_status md_stats(md_system* s, md_stats_t* out);
 
+/* Per-phase GPU time of md_step, from HIP events recorded on the system's
+ * stream around each phase of every step while profiling is enabled:
+ * integrate (half kick + drift + rebuild test), rebuild (cell sort and list
+ * build kernels, which return at once when no rebuild is due) and force (the
+ * force pass, including the fused closing half kick; for the edge mode also
+ * the separate kick kernel).  Times are summed over the steps taken since
+ * profiling was enabled. */
+typedef struct {
+    int64_t steps;
+    double integrate_ms, rebuild_ms, force_ms;
+} md_profile_t;
+
+/* Enables (on != 0) or disables event timing of md_step and clears the sums.
+ * Creates its events lazily; costs one event record per phase and step. */
+md_status md_profile_enable(md_system* s, int32_t on);
+
+/* Reads the sums (syncs). */
+md_status md_profile_read(md_system* s, md_profile_t* out);
+
 /* Destroy the handle (does not free the caller's buffers). */
 void md_destroy(md_system* s);
 

@@ -144,6 +144,23 @@ struct md_system {
     long long steps = 0;
     int edge_grid = 1;
     std::string err;
+    // md_step phase timing (md_profile_enable)
+    bool profiling = false;
+    std::vector<hipEvent_t> events;  // 4 per step of the current md_step call
+    md_profile_t prof{};
+
+    ~md_system() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
+    hipError_t ensure_events(size_t count) {
+        while (events.size() < count) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            events.push_back(e);
+        }
+        return hipSuccess;
+    }
 
     md_status fail(md_status st, const std::string& msg) {
         err = msg;
@@ -377,14 +394,54 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     }
     const md::Sys& y = s->sys;
     bool edge = mode == MD_MODE_EDGE;
+    bool prof = s->profiling;
+    if (prof) {
+        md_status r = s->hip(s->ensure_events(4 * (size_t)nsteps), "profile events");
+        if (r != MD_OK) return r;
+    }
+    hipStream_t st = s->stream;
     for (int k = 0; k < nsteps; k++) {
-        hipError_t e = md::launch_kick_drift(y, edge, s->stream);
-        if (e == hipSuccess) e = md::launch_rebuild(y, s->stream, true, true);
-        if (e == hipSuccess) e = md::launch_forces(y, mode, s->p.prec, true, s->stream, s->edge_grid);
+        hipEvent_t* ev = prof ? &s->events[4 * (size_t)k] : nullptr;
+        hipError_t e = prof ? hipEventRecord(ev[0], st) : hipSuccess;
+        if (e == hipSuccess) e = md::launch_kick_drift(y, edge, st);
+        if (e == hipSuccess && prof) e = hipEventRecord(ev[1], st);
+        if (e == hipSuccess) e = md::launch_rebuild(y, st, true, true);
+        if (e == hipSuccess && prof) e = hipEventRecord(ev[2], st);
+        if (e == hipSuccess) e = md::launch_forces(y, mode, s->p.prec, true, st, s->edge_grid);
+        if (e == hipSuccess && prof) e = hipEventRecord(ev[3], st);
         if (e != hipSuccess) return s->hip(e, "step launch");
     }
     s->steps += nsteps;
-    return s->sync_check();
+    md_status r = s->sync_check();
+    if (r != MD_OK || !prof) return r;
+    for (int k = 0; k < nsteps; k++) {
+        hipEvent_t* ev = &s->events[4 * (size_t)k];
+        float a = 0, b = 0, c = 0;
+        hipError_t e = hipEventElapsedTime(&a, ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[1], ev[2]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[2], ev[3]);
+        if (e != hipSuccess) return s->hip(e, "profile elapsed");
+        s->prof.integrate_ms += a;
+        s->prof.rebuild_ms += b;
+        s->prof.force_ms += c;
+    }
+    s->prof.steps += nsteps;
+    return MD_OK;
+}
+
+md_status md_profile_enable(md_system* s, int32_t on) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    s->profiling = on != 0;
+    s->prof = md_profile_t{};
+    return MD_OK;
+}
+
+md_status md_profile_read(md_system* s, md_profile_t* out) {
+    if (!s || !out) return MD_ERR_INVALID_ARG;
+    md_status r = s->hip(hipStreamSynchronize(s->stream), "profile sync");
+    if (r != MD_OK) return r;
+    *out = s->prof;
+    return MD_OK;
 }
 
 md_status md_energy(md_system* s, double* e_kin, double* e_pot, double* virial) {

@@ -51,6 +51,11 @@ class MDStats(ctypes.Structure):
                 ("n_cells", ctypes.c_int32)]
 
 
+class MDProfile(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("integrate_ms", ctypes.c_double),
+                ("rebuild_ms", ctypes.c_double), ("force_ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _sys_p = ctypes.c_void_p
@@ -70,6 +75,8 @@ _SIGS = {
     "md_get_pairs": ([_sys_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
                       ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "md_stats": ([_sys_p, ctypes.POINTER(MDStats)], ctypes.c_int),
+    "md_profile_enable": ([_sys_p, ctypes.c_int32], ctypes.c_int),
+    "md_profile_read": ([_sys_p, ctypes.POINTER(MDProfile)], ctypes.c_int),
     "md_destroy": ([_sys_p], None),
     "md_status_str": ([ctypes.c_int32], ctypes.c_char_p),
     "md_last_error": ([_sys_p], ctypes.c_char_p),
@@ -210,6 +217,15 @@ class System:
                                       cnt.value, ctypes.byref(cnt)), "md_get_pairs")
         out = out[:cnt.value]
         return out[np.lexsort((out[:, 1], out[:, 0]))]
+
+    def profile(self, on: bool = True):
+        self._check(_lib.md_profile_enable(self._h, int(on)), "md_profile_enable")
+
+    def profile_read(self) -> dict:
+        p = MDProfile()
+        self._check(_lib.md_profile_read(self._h, ctypes.byref(p)), "md_profile_read")
+        return dict(steps=p.steps, integrate_ms=p.integrate_ms, rebuild_ms=p.rebuild_ms,
+                    force_ms=p.force_ms)
 
     def stats(self) -> dict:
         s = MDStats()
