@@ -100,6 +100,8 @@ typedef struct {
     int64_t pairs;          /* half-list entries |E| at the last build             */
     int32_t max_list_len;   /* longest full list at the last build                 */
     int32_t n_cells;        /* cells per box side                                  */
+    int32_t tiles_total;    /* tiles of the vertex pass                            */
+    int32_t tiles_staged;   /* tiles whose neighbour region was staged in LDS      */
 } md_stats_t;
 
 /* Sizes of the two device buffers a system needs (pure host, no HIP call).

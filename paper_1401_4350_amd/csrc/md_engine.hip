@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/md.h"
+#include "md.h"
 #include "md_internal.h"
 
 namespace {
@@ -24,8 +24,9 @@ struct Layout {
     uint64_t pos, vel, frc, quat, angm, trq, id;
     // workspace offsets
     uint64_t xbuild, tpos, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
-        ncount, hcount, hstart, hj, chunk_row, bsum, epart, wpart, kpart, red, ctrl;
-    int nc = 0, ncell = 0, nblk = 0;
+        ncount, hcount, hstart, hj, chunk_row, bsum, epart, wpart, kpart, red, ctrl, tile_seg,
+        tile_nseg, tile_chunk, tile_nchunk;
+    int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
     long long max_half = 0;
 };
 
@@ -38,7 +39,7 @@ uint64_t take(uint64_t& cur, uint64_t bytes) {
 md_status validate(const md_params* p) {
     if (!p) return MD_ERR_INVALID_ARG;
     auto fin = [](double v) { return std::isfinite(v); };
-    if (p->n < 2 || p->max_neighbors < 1) return MD_ERR_INVALID_ARG;
+    if (p->n < 2 || p->n > (1 << 24) || p->max_neighbors < 1) return MD_ERR_INVALID_ARG;
     if (p->pot != MD_POT_LJ && p->pot != MD_POT_PATCHY) return MD_ERR_INVALID_ARG;
     if (p->prec < MD_PREC_FP64 || p->prec > MD_PREC_FP32_KAHAN) return MD_ERR_INVALID_ARG;
     if (!fin(p->box) || !(p->box > 0)) return MD_ERR_INVALID_ARG;
@@ -77,6 +78,17 @@ Layout layout(const md_params& p) {
     L.ncell = nc * nc * nc;
     L.nblk = (int)((n + md::kBlock - 1) / md::kBlock);
     L.max_half = (long long)n * p.max_neighbors / 2 + kSlack;
+    L.ntiles = (int)((n + md::kTile - 1) / md::kTile);
+    {
+        // LDS region of a tile: the 3 x 3 rows of cells around its home cells,
+        // about 9 (H + 2) cells of m particles for H home cells; 1.5x margin,
+        // tiles that still do not fit use global gathers.
+        double m = (double)n / L.ncell;
+        double h = md::kTile / std::max(m, 1e-3) + 1.0;
+        double expect = 9.0 * (h + 2.0) * m;
+        int cap = (int)std::ceil(1.5 * expect / 64.0) * 64;
+        L.lds_cap = std::min(std::max(cap, 512), md::kLdsCapMax);
+    }
     bool patchy = p.pot == MD_POT_PATCHY;
     uint64_t d4 = 32 * n;
     uint64_t cur = 0;
@@ -101,13 +113,17 @@ Layout layout(const md_params& p) {
     L.ccount = take(cur, 4 * (uint64_t)L.ncell);
     L.cstart = take(cur, 4 * ((uint64_t)L.ncell + 1));
     L.order = take(cur, 4 * n);
-    L.nbr = take(cur, 4 * n * (uint64_t)p.max_neighbors);
+    L.nbr = take(cur, 4 * (uint64_t)L.ntiles * md::kTile * 4 * ((p.max_neighbors + 3) / 4));
     L.ncount = take(cur, 4 * n);
     L.hcount = take(cur, 4 * n);
     L.hstart = take(cur, 4 * (n + 1));
     L.hj = take(cur, 4 * (uint64_t)L.max_half);
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
     L.bsum = take(cur, 4 * (uint64_t)L.nblk);
+    L.tile_seg = take(cur, 16 * (uint64_t)L.ntiles * md::kSegMax);
+    L.tile_nseg = take(cur, 4 * (uint64_t)L.ntiles);
+    L.tile_chunk = take(cur, 16 * (uint64_t)L.ntiles * md::kChunkMax);
+    L.tile_nchunk = take(cur, 4 * (uint64_t)L.ntiles);
     L.epart = take(cur, 8 * n);
     L.wpart = take(cur, 8 * n);
     L.kpart = take(cur, 8 * n);
@@ -178,6 +194,8 @@ struct md_system {
         md::Ctrl c;
         st = hip(hipMemcpy(&c, sys.ctrl, sizeof c, hipMemcpyDeviceToHost), "hipMemcpy(ctrl)");
         if (st != MD_OK) return st;
+        if (c.overflow & 2)
+            return fail(MD_ERR_STATE, "internal: a tile region misses a neighbour cell");
         if (c.overflow)
             return fail(MD_ERR_NEIGHBOR_OVERFLOW,
                         "a Verlet list exceeded max_neighbors=" + std::to_string(p.max_neighbors) +
@@ -225,6 +243,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.nc = L.nc;
     y.ncell = L.ncell;
     y.cap = p->max_neighbors;
+    y.mcap = (p->max_neighbors + 3) / 4;
     y.pot = p->pot;
     y.nblk = L.nblk;
     y.max_half = L.max_half;
@@ -267,6 +286,12 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.hj = (int*)(W + L.hj);
     y.chunk_row = (int*)(W + L.chunk_row);
     y.bsum = (int*)(W + L.bsum);
+    y.ntiles = L.ntiles;
+    y.lds_cap = L.lds_cap;
+    y.tile_seg = (int4*)(W + L.tile_seg);
+    y.tile_nseg = (int*)(W + L.tile_nseg);
+    y.tile_chunk = (int4*)(W + L.tile_chunk);
+    y.tile_nchunk = (int*)(W + L.tile_nchunk);
     y.epart = (double*)(W + L.epart);
     y.wpart = (double*)(W + L.wpart);
     y.kpart = (double*)(W + L.kpart);
@@ -508,12 +533,19 @@ md_status md_get_state(md_system* s, double* x, double* v, double* f, double* q,
         r = s->hip(hipMemcpy(buf.data(), it.src, sizeof(double4) * (size_t)n, hipMemcpyDeviceToHost),
                    "download state");
         if (r != MD_OK) break;
+        bool is_pos = it.src == s->sys.pos;  // unwrapped between builds: wrap into [0, L)
+        double L = s->p.box;
         for (int k = 0; k < n; k++) {
             double* d = it.dst + (size_t)it.width * id[k];
             d[0] = buf[k].x;
             d[1] = buf[k].y;
             d[2] = buf[k].z;
             if (it.width == 4) d[3] = buf[k].w;
+            if (is_pos)
+                for (int c = 0; c < 3; c++) {
+                    if (d[c] >= L) d[c] -= L;
+                    if (d[c] < 0) d[c] += L;
+                }
         }
     }
     if (r != MD_OK) return r;
@@ -541,7 +573,7 @@ md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pai
     int64_t w = 0;
     for (int i = 0; i < n && w < cap; i++)
         for (int k = hs[i]; k < hs[i + 1] && w < cap; k++) {
-            int a = id[i], b = id[hj[k]];
+            int a = id[i], b = id[hj[k] & ((1 << 24) - 1)];  // low 24 bits: slot
             pairs[2 * w] = std::min(a, b);
             pairs[2 * w + 1] = std::max(a, b);
             w++;
@@ -560,6 +592,8 @@ md_status md_stats(md_system* s, md_stats_t* out) {
     out->pairs = c.npairs;
     out->max_list_len = c.max_count;
     out->n_cells = s->lay.nc;
+    out->tiles_total = s->lay.ntiles;
+    out->tiles_staged = c.staged;
     return MD_OK;
 }
 

@@ -11,6 +11,18 @@ constexpr int kBlock = 256;  // threads per block of the per-particle kernels
 constexpr int kWave = 64;    // CDNA wavefront
 constexpr int kScanThreads = 1024;
 
+// LDS-staged vertex pass: the particles are cut into tiles of kTile
+// consecutive slots; for each tile the list build records up to kSegMax slot
+// ranges that cover the 27-cell neighbourhoods of its home cells, and list
+// entries of the tile index into that concatenation, which the force pass
+// copies into LDS with coalesced loads.  Tiles whose region does not fit fall
+// back to global gathers.
+constexpr int kTile = 64;
+constexpr int kTileTpp = kBlock / kTile;  // lanes per particle in the tiled pass
+constexpr int kSegMax = 32;
+constexpr int kChunkMax = 96;
+constexpr int kLdsCapMax = 4096;  // particles per tile region (3 doubles each)
+
 // Device-resident control block (one per system).  Written by kernels, read by
 // the host only at syncing calls.
 struct Ctrl {
@@ -18,6 +30,8 @@ struct Ctrl {
     int overflow;       // sticky: a list exceeded its capacity
     int nonfinite;      // sticky: a force or position was NaN/Inf
     int max_count;      // longest full list at the last build
+    int staged;         // tiles of the last build whose region fits in LDS
+    int pad0;
     long long npairs;   // half-list entries at the last build (clamped to capacity)
     long long rebuilds; // number of builds
     long long pad[4];
@@ -42,6 +56,7 @@ struct Sys {
     int nc;         // cells per side
     int ncell;      // nc^3
     int cap;        // full-list capacity per particle
+    int mcap;       // ceil(cap / 4): rows of four entries per particle
     int pot;        // 0 LJ, 1 patchy
     int nblk;       // ceil(n / kBlock)
     long long max_half;  // half-list capacity (entries)
@@ -76,13 +91,19 @@ struct Sys {
     int* ccount;
     int* cstart;     // ncell + 1
     int* order;
-    int* nbr;        // ELL: nbr[k * n + i], k < cap
+    int* nbr;        // full lists, tiled (see list_row in the kernels)
     int* ncount;
     int* hcount;
     int* hstart;     // n + 1
     int* hj;         // half-list partner slots, CSR by row
     int* chunk_row;  // first row of every 64-pair chunk of the half list
     int* bsum;       // per-block half counts, then offsets
+    int ntiles;      // ceil(n / kTile)
+    int lds_cap;     // region capacity (particles) of a tile staged in LDS
+    int4* tile_seg;  // [ntiles * kSegMax]: (slot begin, slot end, LDS base, image code)
+    int* tile_nseg;  // segments of the tile, or -1 for global gathers
+    int4* tile_chunk;  // [ntiles * kChunkMax]: segments cut into runs of <= kWave slots
+    int* tile_nchunk;
     double* epart;   // per-particle potential energy
     double* wpart;   // per-particle virial
     double* kpart;   // per-particle kinetic energy

@@ -36,6 +36,61 @@ __device__ __forceinline__ double wrap_delta(double d, double box, double inv_bo
     return d - box * rint(d * inv_box);
 }
 
+// Positions are kept unwrapped between list builds (they move by less than
+// half a skin), and wrapped into [0, L) when the cells are rebuilt.  A list
+// entry therefore fixes the periodic image of the pair for the lifetime of the
+// list: entry = slot j | (s_x + 1) << 24 | (s_y + 1) << 26 | (s_z + 1) << 28,
+// with the separation x_j - x_i + s L.  One select per axis replaces the
+// divide-and-round of the minimum-image convention in the hot loops.
+constexpr int kSlotBits = 24;
+constexpr int kSlotMask = (1 << kSlotBits) - 1;
+
+__device__ __forceinline__ int entry_slot(int e) { return e & kSlotMask; }
+
+// Full lists are stored per tile: entry k of particle i (tile t = i / kTile,
+// p = i % kTile) sits at word ((t * mcap + k / 4) * kTile + p) * 4 + k % 4.
+// A tile's lists are one contiguous block, and four lanes that share a
+// particle read 16 consecutive bytes, so a wavefront's load is one contiguous
+// 256-byte run.  list_row(s, i) points at entry 0 of particle i; entry k is
+// at offset list_off(k).
+__device__ __forceinline__ const int* list_row(const Sys& s, int i) {
+    return s.nbr + (((size_t)(i / kTile) * s.mcap) * kTile + (i % kTile)) * 4;
+}
+__device__ __forceinline__ int* list_row_w(const Sys& s, int i) {
+    return s.nbr + (((size_t)(i / kTile) * s.mcap) * kTile + (i % kTile)) * 4;
+}
+__device__ __forceinline__ size_t list_off(int k) { return (size_t)(k >> 2) * (kTile * 4) + (k & 3); }
+
+__device__ __forceinline__ double image(int e, int axis, double box) {
+    int c = (e >> (kSlotBits + 2 * axis)) & 3;
+    return c == 1 ? 0.0 : (c == 0 ? -box : box);
+}
+
+__device__ __forceinline__ int image_code(double d, double inv_box) {
+    return (int)(-rint(d * inv_box)) + 1;
+}
+
+__device__ __forceinline__ double wrap_box(double y, double L) {
+    if (y >= L) y -= L;
+    if (y < 0) y += L;
+    return y;
+}
+
+// 1/a from the hardware reciprocal refined by two Newton steps (to within an
+// ulp of the correctly rounded quotient for normal a).
+__device__ __forceinline__ double rcp_nr(double a) {
+    double y = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-a, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ float rcp_nr(float a) {
+    float y = __builtin_amdgcn_rcpf(a);
+    float e = fmaf(-a, y, 1.0f);
+    return fmaf(y, e, y);
+}
+
 __device__ __forceinline__ int cell_coord(double x, double cell_inv, int nc) {
     int c = (int)(x * cell_inv);
     c = c < 0 ? 0 : c;
@@ -195,9 +250,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) {
     int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= s.n) return;
     double4 x = s.pos[p];
-    int cx = cell_coord(x.x, s.cell_inv, s.nc);
-    int cy = cell_coord(x.y, s.cell_inv, s.nc);
-    int cz = cell_coord(x.z, s.cell_inv, s.nc);
+    int cx = cell_coord(wrap_box(x.x, s.box), s.cell_inv, s.nc);
+    int cy = cell_coord(wrap_box(x.y, s.box), s.cell_inv, s.nc);
+    int cz = cell_coord(wrap_box(x.z, s.box), s.cell_inv, s.nc);
     int c = (cz * s.nc + cy) * s.nc + cx;
     s.cell[p] = c;
     s.rank[p] = atomicAdd(&s.ccount[c], 1);
@@ -230,7 +285,10 @@ __global__ __launch_bounds__(kScanThreads) void k_cell_scan(Sys s) {
         s.ccount[k] = 0;
     }
     if (t == kScanThreads - 1) s.cstart[s.ncell] = sh[t];
-    if (t == 0) s.ctrl->max_count = 0;  // the list build that follows records its maximum
+    if (t == 0) {  // the list build that follows records its maximum and staged tiles
+        s.ctrl->max_count = 0;
+        s.ctrl->staged = 0;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_scatter(Sys s) {
@@ -264,13 +322,165 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Sys s) {
     int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= s.n) return;
     int p = s.order[k];
-    s.tpos[k] = s.pos[p];
+    double4 x = s.pos[p];
+    s.tpos[k] = make_double4(wrap_box(x.x, s.box), wrap_box(x.y, s.box), wrap_box(x.z, s.box), 0.0);
     s.tvel[k] = s.vel[p];
     s.tid[k] = s.id[p];
     if (s.pot == 1) {
         s.tquat[k] = s.quat[p];
         s.tangm[k] = s.angm[p];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Tile regions for the LDS-staged vertex pass (one thread per tile of kTile
+// consecutive slots).  The tile's home cells form a contiguous run of cell
+// ids; their 27-cell neighbourhoods are, row by row, x-intervals of cells,
+// i.e. contiguous slot ranges.  The ranges are sorted and merged into at most
+// kSegMax disjoint segments whose concatenation is the tile's LDS image.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int cell_of_slot(const int* cstart, int ncell, int slot) {
+    int lo = 0, hi = ncell;  // largest c with cstart[c] <= slot
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (cstart[mid] <= slot) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+constexpr int kIvMax = 72;
+constexpr int kHomeMax = 24;
+
+__global__ __launch_bounds__(kBlock) void k_tiles(Sys s) {
+    if (!s.ctrl->rebuild) return;
+    int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= s.ntiles) return;
+    int nc = s.nc;
+    if (s.pot != 0 || nc < 3) {
+        s.tile_nseg[t] = -1;
+        return;
+    }
+    int a = t * kTile;
+    int b = min(a + kTile, s.n) - 1;
+    int c0 = cell_of_slot(s.cstart, s.ncell, a);
+    int c1 = cell_of_slot(s.cstart, s.ncell, b);
+    if (c1 - c0 + 1 > kHomeMax) {
+        s.tile_nseg[t] = -1;
+        return;
+    }
+    // intervals: (slot begin, slot end, periodic image code, 0); the image is
+    // the shift that brings the cells next to the tile's home cells, so the
+    // LDS copy can be stored already shifted
+    int4 iv[kIvMax];
+    int niv = 0;
+    bool over = false;
+    auto add = [&](int row, int lo, int hi, int code) {
+        int b0 = s.cstart[row * nc + lo], b1 = s.cstart[row * nc + hi + 1];
+        if (b1 <= b0) return;
+        if (niv == kIvMax) {
+            over = true;
+            return;
+        }
+        iv[niv++] = make_int4(b0, b1, code, 0);
+    };
+    auto wrapc = [&](int v) { return v < 0 ? 0 : (v >= nc ? 2 : 1); };  // shift -L, 0, +L
+    int r0 = c0 / nc, r1 = c1 / nc;
+    for (int r = r0; r <= r1 && !over; r++) {
+        int xa = r == r0 ? c0 % nc : 0;
+        int xb = r == r1 ? c1 % nc : nc - 1;
+        int y = r % nc, z = r / nc;
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++) {
+                int rr = ((z + dz + nc) % nc) * nc + (y + dy + nc) % nc;
+                int yz = wrapc(y + dy) << 2 | wrapc(z + dz) << 4;
+                int lo = xa - 1, hi = xb + 1;
+                if (hi - lo + 1 >= nc) {
+                    over = true;  // a full row seen through two x images
+                } else if (lo < 0) {
+                    add(rr, lo + nc, nc - 1, yz | 0);
+                    add(rr, 0, hi, yz | 1);
+                } else if (hi >= nc) {
+                    add(rr, lo, nc - 1, yz | 1);
+                    add(rr, 0, hi - nc, yz | 2);
+                } else {
+                    add(rr, lo, hi, yz | 1);
+                }
+            }
+    }
+    if (over) {
+        s.tile_nseg[t] = -1;
+        return;
+    }
+    // sort by (image, start); merge overlapping or touching ranges of one image
+    for (int k = 1; k < niv; k++) {
+        int4 v = iv[k];
+        int m = k - 1;
+        while (m >= 0 && (iv[m].z > v.z || (iv[m].z == v.z && iv[m].x > v.x))) {
+            iv[m + 1] = iv[m];
+            m--;
+        }
+        iv[m + 1] = v;
+    }
+    int4* seg = s.tile_seg + (size_t)t * kSegMax;
+    int nseg = 0, base = 0;
+    int cb = -1, ce = -1, cc = -1;
+    for (int k = 0; k <= niv; k++) {
+        if (k < niv && cb >= 0 && iv[k].z == cc && iv[k].x <= ce) {
+            ce = max(ce, iv[k].y);
+            continue;
+        }
+        if (cb >= 0) {
+            if (nseg == kSegMax || base + (ce - cb) > s.lds_cap) {
+                s.tile_nseg[t] = -1;
+                return;
+            }
+            seg[nseg++] = make_int4(cb, ce, base, cc);
+            base += ce - cb;
+        }
+        if (k < niv) {
+            cb = iv[k].x;
+            ce = iv[k].y;
+            cc = iv[k].z;
+        }
+    }
+    // copy chunks of at most one wavefront each (a segment split into runs of
+    // kWave slots), consumed by the fill of the force pass without searching
+    int4* chk = s.tile_chunk + (size_t)t * kChunkMax;
+    int nchk = 0;
+    for (int q = 0; q < nseg; q++) {
+        int4 g = seg[q];
+        for (int b = g.x; b < g.y; b += kWave) {
+            if (nchk == kChunkMax) {
+                s.tile_nseg[t] = -1;
+                return;
+            }
+            chk[nchk++] = make_int4(b, min(g.y, b + kWave), g.z + (b - g.x), g.w);
+        }
+    }
+    s.tile_nchunk[t] = nchk;
+    s.tile_nseg[t] = nseg;
+    atomicAdd(&s.ctrl->staged, 1);
+}
+
+// Position of slot range [cb, ...) seen through image `code` inside a tile's
+// LDS image: base + (cb - begin) of the segment that holds it, or -1.
+__device__ __forceinline__ int tile_lds_base(const int4* seg, int nseg, int cb, int code) {
+    for (int q = 0; q < nseg; q++) {
+        int4 g = seg[q];
+        if (g.w == code && cb >= g.x && cb < g.y) return g.z + (cb - g.x);
+    }
+    return -1;
+}
+
+// Global slot of LDS index idx of a tile.
+__device__ __forceinline__ int tile_slot(const int4* seg, int nseg, int idx) {
+    for (int q = 0; q < nseg; q++) {
+        int4 g = seg[q];
+        if (idx >= g.z && idx < g.z + (g.y - g.x)) return g.x + (idx - g.z);
+    }
+    return -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -305,27 +515,45 @@ __global__ __launch_bounds__(kBlock) void k_build(Sys s) {
         int span = nc >= 3 ? 3 : nc;   // distinct cells per dimension
         int lo = nc >= 3 ? -1 : 0;
         int count = 0;
+        // staged tile: entries index the tile's LDS image instead of slots
+        const int tile = i / kTile;
+        const int nseg = s.tile_nseg[tile];
+        const int4* seg = s.tile_seg + (size_t)tile * kSegMax;
         for (int dz = 0; dz < span; dz++) {
             int az = cz + lo + dz;
+            int wz = az < 0 ? 0 : (az >= nc ? 2 : 1);  // image of the cell row
             az = az < 0 ? az + nc : (az >= nc ? az - nc : az);
             for (int dy = 0; dy < span; dy++) {
                 int ay = cy + lo + dy;
+                int wy = ay < 0 ? 0 : (ay >= nc ? 2 : 1);
                 ay = ay < 0 ? ay + nc : (ay >= nc ? ay - nc : ay);
                 for (int dx = 0; dx < span; dx++) {
                     int ax = cx + lo + dx;
+                    int wx = ax < 0 ? 0 : (ax >= nc ? 2 : 1);
                     ax = ax < 0 ? ax + nc : (ax >= nc ? ax - nc : ax);
                     int c = (az * nc + ay) * nc + ax;
                     int e = s.cstart[c + 1];
-                    for (int j = s.cstart[c]; j < e; j++) {
+                    int cb = s.cstart[c];
+                    int rel = 0;  // entry value = j - rel
+                    if (nseg >= 0 && cb < e) {
+                        int base = tile_lds_base(seg, nseg, cb, wx | wy << 2 | wz << 4);
+                        if (base < 0) atomicOr(&s.ctrl->overflow, 2);  // region misses a cell
+                        rel = cb - base;
+                    }
+                    for (int j = cb; j < e; j++) {
                         if (j == i) continue;
                         double4 xj = s.tpos[j];
-                        double ddx = wrap_delta(xj.x - xi.x, s.box, s.inv_box);
-                        double ddy = wrap_delta(xj.y - xi.y, s.box, s.inv_box);
-                        double ddz = wrap_delta(xj.z - xi.z, s.box, s.inv_box);
+                        double ex = xj.x - xi.x, ey = xj.y - xi.y, ez = xj.z - xi.z;
+                        double ddx = wrap_delta(ex, s.box, s.inv_box);
+                        double ddy = wrap_delta(ey, s.box, s.inv_box);
+                        double ddz = wrap_delta(ez, s.box, s.inv_box);
                         double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                         if (r2 < s.rv2) {
                             if (count < s.cap) {
-                                s.nbr[(size_t)count * s.n + i] = j;
+                                int code = image_code(ex, s.inv_box) |
+                                           image_code(ey, s.inv_box) << 2 |
+                                           image_code(ez, s.inv_box) << 4;
+                                list_row_w(s, i)[list_off(count)] = (j - rel) | code << kSlotBits;
                                 half += (j > i);
                             }
                             count++;
@@ -412,9 +640,14 @@ __global__ __launch_bounds__(kBlock) void k_half_fill(Sys s) {
     if (i == s.n - 1) s.hstart[s.n] = (int)end;
     long long k = start;
     int cnt = s.ncount[i];
+    const int tile = i / kTile;
+    const int nseg = s.tile_nseg[tile];
+    const int4* seg = s.tile_seg + (size_t)tile * kSegMax;
     for (int m = 0; m < cnt && k < end; m++) {
-        int j = s.nbr[(size_t)m * s.n + i];
-        if (j > i) s.hj[k++] = j;
+        int ent = list_row(s, i)[list_off(m)];
+        int j = entry_slot(ent);
+        if (nseg >= 0) j = tile_slot(seg, nseg, j);  // tile-relative -> slot
+        if (j > i) s.hj[k++] = j | (ent & ~kSlotMask);
     }
     for (long long c0 = (start + kWave - 1) / kWave * kWave; c0 < end; c0 += kWave)
         s.chunk_row[c0 / kWave] = i;
@@ -437,6 +670,9 @@ struct Acc3 {
         y += b;
         z += c;
     }
+    __device__ double gx() const { return x; }
+    __device__ double gy() const { return y; }
+    __device__ double gz() const { return z; }
 };
 template <>
 struct Acc3<2> {
@@ -452,50 +688,264 @@ struct Acc3<2> {
         k(y, cy, b);
         k(z, cz, c);
     }
+    // compensated value: the running sum minus the carried rounding error
+    __device__ double gx() const { return (double)x - (double)cx; }
+    __device__ double gy() const { return (double)y - (double)cy; }
+    __device__ double gz() const { return (double)z - (double)cz; }
 };
 
-template <int PREC, bool KICK, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) {
-    const LJc<double>& c64 = s.l64;
-    const LJc<float>& c32 = s.l32;
-    using R = typename std::conditional<PREC == 0, double, float>::type;
-    int lb = xcd_remap(blockIdx.x, gridDim.x);
-    int i = lb * kBlock + threadIdx.x;
-    if (KICK && blockIdx.x == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
-    if (i >= s.n) return;
-    double4 xi = s.pos[i];
-    int cnt = s.ncount[i];
-    Acc3<PREC> f;
-    double e = 0, w = 0;
-    const int* nb = s.nbr + i;
-    for (int k = 0; k < cnt; k++) {
-        int j = nb[(size_t)k * s.n];
-        double4 xj = s.pos[j];
-        double dx = wrap_delta(xj.x - xi.x, s.box, s.inv_box);
-        double dy = wrap_delta(xj.y - xi.y, s.box, s.inv_box);
-        double dz = wrap_delta(xj.z - xi.z, s.box, s.inv_box);
-        double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < s.rc2) {
-            if (PREC == 0) {
-                double v;
-                double fr = lj_fr<double>(r2, c64, ENERGY ? &v : nullptr);
-                f.add(-fr * dx, -fr * dy, -fr * dz);
-                if (ENERGY) {
-                    e += 0.5 * v;
-                    w += 0.5 * fr * r2;
-                }
-            } else {
-                float v;
-                float fr = lj_fr<float>((float)r2, c32, ENERGY ? &v : nullptr);
-                f.add(-fr * (float)dx, -fr * (float)dy, -fr * (float)dz);
-                if (ENERGY) {
-                    e += 0.5 * (double)v;
-                    w += 0.5 * (double)fr * r2;
-                }
-            }
+#ifndef MD_VERTEX_TPP
+#define MD_VERTEX_TPP 1
+#endif
+#ifndef MD_VERTEX_UNROLL
+#define MD_VERTEX_UNROLL 4
+#endif
+constexpr int kVertexTpp = MD_VERTEX_TPP;        // lanes per particle, LJ vertex pass
+constexpr int kVertexUnroll = MD_VERTEX_UNROLL;  // gathers in flight per lane
+
+// One list entry of the LJ vertex pass.  Branch-free: entries beyond r_c
+// contribute an exact zero.  The separation is formed in FP64, with the
+// entry's stored image (global gathers) or from an LDS copy that already
+// carries the image (PRESHIFTED); PREC > 0 does the rest in FP32.
+template <int PREC, bool ENERGY, bool PRESHIFTED = false>
+__device__ __forceinline__ void lj_vertex_term(const Sys& s, const double4& xi, int ent,
+                                               const double4& xj, Acc3<PREC>& f, double& e,
+                                               double& w) {
+    double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+    if (!PRESHIFTED) {
+        dx += image(ent, 0, s.box);
+        dy += image(ent, 1, s.box);
+        dz += image(ent, 2, s.box);
+    }
+    double r2 = dx * dx + dy * dy + dz * dz;
+    bool in = r2 < s.rc2;
+    if (PREC == 0) {
+        double inv = rcp_nr(r2);
+        double s2 = s.l64.sig2 * inv;
+        double s6 = s2 * s2 * s2;
+        double fr = in ? s.l64.eps24 * inv * s6 * (2.0 * s6 - 1.0) : 0.0;
+        f.add(-fr * dx, -fr * dy, -fr * dz);
+        if (ENERGY && in) {
+            e += 0.5 * (s.l64.eps4 * s6 * (s6 - 1.0) - s.l64.vshift);
+            w += 0.5 * fr * r2;
+        }
+    } else {
+        float r2f = (float)r2;
+        float inv = rcp_nr(r2f);
+        float s2 = s.l32.sig2 * inv;
+        float s6 = s2 * s2 * s2;
+        float fr = in ? s.l32.eps24 * inv * s6 * (2.0f * s6 - 1.0f) : 0.0f;
+        f.add(-fr * (float)dx, -fr * (float)dy, -fr * (float)dz);
+        if (ENERGY && in) {
+            e += 0.5 * (double)(s.l32.eps4 * s6 * (s6 - 1.0f) - s.l32.vshift);
+            w += 0.5 * (double)fr * r2;
         }
     }
-    double fx = f.x, fy = f.y, fz = f.z;
+}
+
+// TPP lanes share particle i and take every TPP-th list entry; each lane
+// keeps kVertexUnroll independent gathers in flight; the TPP partial sums are
+// combined with cross-lane shuffles before the single owner write.
+// Walks entries q, q + TPP, ... of particle i's list with global gathers
+// (tiles whose region was not staged).
+template <int PREC, int TPP, bool ENERGY>
+__device__ __forceinline__ void lj_walk_global(const Sys& s, int ii, int q, int cnt,
+                                               const double4& xi, Acc3<PREC>& f, double& e,
+                                               double& w) {
+    constexpr int U = kVertexUnroll;
+    const int* nb = list_row(s, ii);
+    int k = q;
+    for (; k + (U - 1) * TPP < cnt; k += U * TPP) {
+        int en[U];
+        double4 xj[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) en[u] = __builtin_nontemporal_load(nb + list_off(k + u * TPP));
+#pragma unroll
+        for (int u = 0; u < U; u++) xj[u] = s.pos[entry_slot(en[u])];
+#pragma unroll
+        for (int u = 0; u < U; u++) lj_vertex_term<PREC, ENERGY>(s, xi, en[u], xj[u], f, e, w);
+    }
+    for (; k < cnt; k += TPP) {
+        int en = __builtin_nontemporal_load(nb + list_off(k));
+        lj_vertex_term<PREC, ENERGY>(s, xi, en, s.pos[entry_slot(en)], f, e, w);
+    }
+}
+
+#ifndef MD_VERTEX_PREFETCH
+#define MD_VERTEX_PREFETCH 24
+#endif
+constexpr int kPrefetch = MD_VERTEX_PREFETCH;  // list entries held in registers per lane
+constexpr double kFar = 1.0e15;                // coordinate of the padding slot
+
+// LDS image of a staged tile: three planes (x, y, z) of `plane` doubles; slot
+// `cap` of every plane is a padding particle far outside the box, so padded
+// list entries give r^2 >> r_c^2 and an exact zero.
+__device__ __forceinline__ int lds_plane(int cap) { return cap + 8; }
+
+// Copy of a staged tile's region into LDS.  Wave v takes chunks v, v + 4, ...
+// (runs of at most 64 slots with one image each, from the list build) in
+// batches of R; chunk descriptors are wave-uniform.  The loads of a batch are
+// issued by region_issue and consumed by region_store, so the caller can put
+// other loads in between: loads retire in order, so the first batch is issued
+// before the (slower) list prefetch and stored right after it.
+struct RegionBatch {
+    static constexpr int R = 8;
+    double4 p[R];
+    int4 d[R];
+};
+
+__device__ __forceinline__ void region_issue(const Sys& s, int tile, int nchk, int c0,
+                                             RegionBatch& b) {
+    constexpr int W = kBlock / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
+#pragma unroll
+    for (int r = 0; r < RegionBatch::R; r++) {
+        int c = c0 + r * W;
+        b.d[r] = c < nchk ? chk[c] : make_int4(0, 1, 0, -1);
+        // unconditional load (lanes past the chunk end re-read its last slot)
+        b.p[r] = s.pos[b.d[r].x + min(lane, b.d[r].y - b.d[r].x - 1)];
+    }
+}
+
+__device__ __forceinline__ void region_store(const Sys& s, double* lds, int plane,
+                                             const RegionBatch& b) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int r = 0; r < RegionBatch::R; r++) {
+        const int4 d = b.d[r];
+        if (d.w >= 0 && lane < d.y - d.x) {
+            int m = d.z + lane;
+            // the chunk's periodic image is added on the way in
+            lds[m] = b.p[r].x + (double)((d.w & 3) - 1) * s.box;
+            lds[plane + m] = b.p[r].y + (double)(((d.w >> 2) & 3) - 1) * s.box;
+            lds[2 * plane + m] = b.p[r].z + (double)(((d.w >> 4) & 3) - 1) * s.box;
+        }
+    }
+}
+
+// Branch-free LJ term from an LDS image that already carries the periodic
+// image.  The cut-off selects a 0/1 factor, so every lane runs the same
+// instruction stream.
+template <int PREC, bool ENERGY>
+__device__ __forceinline__ void lj_lds_term(const Sys& s, const double* lds, int plane, int k,
+                                            const double4& xi, Acc3<PREC>& f, double& e,
+                                            double& w) {
+    double dx = lds[k] - xi.x;
+    double dy = lds[plane + k] - xi.y;
+    double dz = lds[2 * plane + k] - xi.z;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    bool in = r2 < s.rc2;
+    if (PREC == 0) {
+        double inv = rcp_nr(r2);
+        double s2 = s.l64.sig2 * inv;
+        double s6 = s2 * s2 * s2;
+        double fr = s.l64.eps24 * inv * s6 * (2.0 * s6 - 1.0) * (in ? 1.0 : 0.0);
+        f.add(-fr * dx, -fr * dy, -fr * dz);
+        if (ENERGY && in) {
+            e += 0.5 * (s.l64.eps4 * s6 * (s6 - 1.0) - s.l64.vshift);
+            w += 0.5 * fr * r2;
+        }
+    } else {
+        float r2f = (float)r2;
+        float inv = rcp_nr(r2f);
+        float s2 = s.l32.sig2 * inv;
+        float s6 = s2 * s2 * s2;
+        float fr = s.l32.eps24 * inv * s6 * (2.0f * s6 - 1.0f) * (in ? 1.0f : 0.0f);
+        f.add(-fr * (float)dx, -fr * (float)dy, -fr * (float)dz);
+        if (ENERGY && in) {
+            e += 0.5 * (double)(s.l32.eps4 * s6 * (s6 - 1.0f) - s.l32.vshift);
+            w += 0.5 * (double)fr * r2;
+        }
+    }
+}
+
+// One workgroup per tile of kTile particles, TPP = kBlock / kTile lanes per
+// particle (lane q of particle i takes entries q, q + TPP, ...).  A staged
+// tile requests the lane's first kPrefetch list entries, copies its region
+// into LDS meanwhile, then evaluates the entries from LDS in groups of four
+// under a wave-uniform trip count (entries past the list end point at the
+// padding slot).  Unstaged tiles gather from global memory.
+template <int PREC, int TPP, bool KICK, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) {
+    static_assert(TPP * kTile == kBlock, "one tile per workgroup");
+    static_assert(kPrefetch % 4 == 0, "groups of four");
+    extern __shared__ double lds[];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = tile * kTile + threadIdx.x / TPP;
+    const int q = threadIdx.x % TPP;
+    if (KICK && blockIdx.x == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
+    const int nseg = s.tile_nseg[tile];
+    const int cap = s.lds_cap;
+    bool act = i < s.n;
+    int ii = act ? i : s.n - 1;  // idle lanes stay for the group shuffle
+    double4 xi = s.pos[ii];
+    int cnt = act ? s.ncount[ii] : 0;
+    Acc3<PREC> f;
+    double e = 0, w = 0;
+    if (nseg >= 0) {
+        constexpr int E = kPrefetch;
+        const int plane = lds_plane(cap);
+        const int* nb = list_row(s, ii);
+        int mine = cnt > q ? (cnt - q + TPP - 1) / TPP : 0;  // entries of this lane
+        int mmax = mine;
+        for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
+        mmax = __builtin_amdgcn_readfirstlane(mmax);
+        // region copy, first batch: issued before the list prefetch
+        constexpr int W = kBlock / kWave;
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        const int nchk = s.tile_nchunk[tile];
+        RegionBatch rb;
+        region_issue(s, tile, nchk, wv, rb);
+        // every lane issues all E loads (past its list end it re-reads its own
+        // first entry), so no load sits behind a branch and all are in flight
+        int en[E];
+#pragma unroll
+        for (int m = 0; m < E; m++) {
+            bool ok = m < mine;
+            int v = __builtin_nontemporal_load(nb + list_off(ok ? q + m * TPP : q));
+            // past the end: all slot bits set, clamped to the padding slot; the
+            // value depends on the load either way, so it is never skipped
+            en[m] = min(entry_slot(v) | (ok ? 0 : kSlotMask), cap);
+        }
+        region_store(s, lds, plane, rb);
+        for (int c0 = wv + W * RegionBatch::R; c0 < nchk; c0 += W * RegionBatch::R) {
+            region_issue(s, tile, nchk, c0, rb);
+            region_store(s, lds, plane, rb);
+        }
+        if (threadIdx.x == 0) {  // padding particle
+            lds[cap] = kFar;
+            lds[plane + cap] = kFar;
+            lds[2 * plane + cap] = kFar;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; m += 4) {
+            if (m < mmax) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) lj_lds_term<PREC, ENERGY>(s, lds, plane, en[m + u], xi, f, e, w);
+            }
+        }
+        for (int m = E; m < mmax; m++) {  // lists longer than the prefetch
+            int k = cap;
+            if (m < mine) k = entry_slot(__builtin_nontemporal_load(nb + list_off(q + m * TPP)));
+            lj_lds_term<PREC, ENERGY>(s, lds, plane, k, xi, f, e, w);
+        }
+    } else {
+        lj_walk_global<PREC, TPP, ENERGY>(s, ii, q, cnt, xi, f, e, w);
+    }
+    double fx = f.gx(), fy = f.gy(), fz = f.gz();
+#pragma unroll
+    for (int off = TPP / 2; off > 0; off >>= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+        if (ENERGY) {
+            e += __shfl_xor(e, off);
+            w += __shfl_xor(w, off);
+        }
+    }
+    if (!act || q != 0) return;
     if (ENERGY) {  // energy pass: leaves the forces of the last force pass alone
         s.epart[i] = e;
         s.wpart[i] = w;
@@ -526,13 +976,14 @@ __global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) {
     int cnt = s.ncount[i];
     Acc3<PREC> f, t;
     double e = 0, w = 0;
-    const int* nb = s.nbr + i;
+    const int* nb = list_row(s, i);
     for (int k = 0; k < cnt; k++) {
-        int j = nb[(size_t)k * s.n];
+        int ent = nb[list_off(k)];
+        int j = entry_slot(ent);
         double4 xj = s.pos[j];
-        double dx = wrap_delta(xj.x - xi.x, s.box, s.inv_box);
-        double dy = wrap_delta(xj.y - xi.y, s.box, s.inv_box);
-        double dz = wrap_delta(xj.z - xi.z, s.box, s.inv_box);
+        double dx = xj.x - xi.x + image(ent, 0, s.box);
+        double dy = xj.y - xi.y + image(ent, 1, s.box);
+        double dz = xj.z - xi.z + image(ent, 2, s.box);
         double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < s.rc2) {
             V3<R> uj[4];
@@ -549,8 +1000,8 @@ __global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) {
             }
         }
     }
-    double fx = f.x, fy = f.y, fz = f.z;
-    double tx = t.x, ty = t.y, tz = t.z;
+    double fx = f.gx(), fy = f.gy(), fz = f.gz();
+    double tx = t.gx(), ty = t.gy(), tz = t.gz();
     if (ENERGY) {
         s.epart[i] = e;
         s.wpart[i] = w;
@@ -627,13 +1078,14 @@ __global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
             for (int q = 0; q < lim; q++) row += (__builtin_amdgcn_readlane(hs, q) <= e);
         }
         const int i = row;
-        const int j = valid ? s.hj[e] : i;
+        const int ent = valid ? s.hj[e] : i;
+        const int j = min(entry_slot(ent), s.n - 1);
         double fx = 0, fy = 0, fz = 0, tix = 0, tiy = 0, tiz = 0, tjx = 0, tjy = 0, tjz = 0;
         if (valid) {
             double4 xi = s.pos[i], xj = s.pos[j];
-            double dx = wrap_delta(xj.x - xi.x, s.box, s.inv_box);
-            double dy = wrap_delta(xj.y - xi.y, s.box, s.inv_box);
-            double dz = wrap_delta(xj.z - xi.z, s.box, s.inv_box);
+            double dx = xj.x - xi.x + image(ent, 0, s.box);
+            double dy = xj.y - xi.y + image(ent, 1, s.box);
+            double dz = xj.z - xi.z + image(ent, 2, s.box);
             double r2 = dx * dx + dy * dy + dz * dz;
             if (r2 < s.rc2) {
                 if (POT == 0) {
@@ -720,12 +1172,6 @@ __global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
 // last build.  Optionally zeroes F (and tau) for the edge pass.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ double wrap_pos(double y, double L) {
-    if (y >= L) y -= L;
-    if (y < 0) y += L;
-    return y;
-}
-
 template <int POT, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(Sys s) {
     int i = blockIdx.x * kBlock + threadIdx.x;
@@ -736,9 +1182,9 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Sys s) {
     v.x += s.hdt * f.x * s.inv_mass;
     v.y += s.hdt * f.y * s.inv_mass;
     v.z += s.hdt * f.z * s.inv_mass;
-    x.x = wrap_pos(x.x + s.dt * v.x, s.box);
-    x.y = wrap_pos(x.y + s.dt * v.y, s.box);
-    x.z = wrap_pos(x.z + s.dt * v.z, s.box);
+    x.x += s.dt * v.x;  // unwrapped until the next list build
+    x.y += s.dt * v.y;
+    x.z += s.dt * v.z;
     s.vel[i] = v;
     s.pos[i] = x;
     if (POT == 1) {
@@ -766,9 +1212,9 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Sys s) {
     }
     if (ZERO) s.frc[i] = make_double4(0, 0, 0, 0);
     double4 xb = s.xbuild[i];
-    double ddx = wrap_delta(x.x - xb.x, s.box, s.inv_box);
-    double ddy = wrap_delta(x.y - xb.y, s.box, s.inv_box);
-    double ddz = wrap_delta(x.z - xb.z, s.box, s.inv_box);
+    double ddx = x.x - xb.x;
+    double ddy = x.y - xb.y;
+    double ddz = x.z - xb.z;
     if (ddx * ddx + ddy * ddy + ddz * ddz > s.disp2) s.ctrl->rebuild = 1;
 }
 
@@ -885,6 +1331,7 @@ hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) 
         hipLaunchKernelGGL(k_reorder, grid_n(s.n), dim3(kBlock), 0, st, s);
     }
     if (lists) {
+        hipLaunchKernelGGL(k_tiles, grid_n(s.ntiles), dim3(kBlock), 0, st, s);
         hipLaunchKernelGGL(k_build, dim3(s.nblk), dim3(kBlock), 0, st, s);
         hipLaunchKernelGGL(k_half_scan, dim3(1), dim3(kScanThreads), 0, st, s);
         hipLaunchKernelGGL(k_half_fill, dim3(s.nblk), dim3(kBlock), 0, st, s);
@@ -911,12 +1358,15 @@ template <int PREC>
 static void vertex_dispatch(const Sys& s, bool kick, bool energy, hipStream_t st) {
     dim3 g(s.nblk), b(kBlock);
     if (s.pot == 0) {
+        constexpr int T = kTileTpp;
+        dim3 gl((unsigned)s.ntiles);
+        size_t sh = 3 * sizeof(double) * (size_t)(s.lds_cap + 8);
         if (kick)
-            hipLaunchKernelGGL((k_vertex_lj<PREC, true, false>), g, b, 0, st, s);
+            hipLaunchKernelGGL((k_vertex_lj<PREC, T, true, false>), gl, b, sh, st, s);
         else if (energy)
-            hipLaunchKernelGGL((k_vertex_lj<PREC, false, true>), g, b, 0, st, s);
+            hipLaunchKernelGGL((k_vertex_lj<PREC, T, false, true>), gl, b, sh, st, s);
         else
-            hipLaunchKernelGGL((k_vertex_lj<PREC, false, false>), g, b, 0, st, s);
+            hipLaunchKernelGGL((k_vertex_lj<PREC, T, false, false>), gl, b, sh, st, s);
     } else {
         if (kick)
             hipLaunchKernelGGL((k_vertex_patchy<PREC, true, false>), g, b, 0, st, s);

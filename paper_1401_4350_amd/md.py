@@ -48,7 +48,8 @@ class MDSizes(ctypes.Structure):
 class MDStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
                 ("pairs", ctypes.c_int64), ("max_list_len", ctypes.c_int32),
-                ("n_cells", ctypes.c_int32)]
+                ("n_cells", ctypes.c_int32), ("tiles_total", ctypes.c_int32),
+                ("tiles_staged", ctypes.c_int32)]
 
 
 class MDProfile(ctypes.Structure):
@@ -231,7 +232,8 @@ class System:
         s = MDStats()
         self._check(_lib.md_stats(self._h, ctypes.byref(s)), "md_stats")
         return dict(steps=s.steps, rebuilds=s.rebuilds, pairs=s.pairs,
-                    max_list_len=s.max_list_len, n_cells=s.n_cells)
+                    max_list_len=s.max_list_len, n_cells=s.n_cells,
+                    tiles_total=s.tiles_total, tiles_staged=s.tiles_staged)
 
 
 def lib():

@@ -92,6 +92,33 @@ def test_forces_fp64(md, case, mode):
     np.testing.assert_allclose(ep, e, rtol=0, atol=1e-12 * np.abs(e).max())
 
 
+TILE_CASES = {
+    "lj20000": ("lj_small", {"n": 20000}, "staged"),              # 10 cells per side
+    "lj_dense_30000": ("lj_many_dense", {"n": 30000}, "staged"),  # 9 cells per side
+    "lj_dilute": ("lj_small", {"n": 2000, "rho": 0.1}, "global"),
+    "lj300_two_cells": ("lj_small", {"n": 300}, "global"),
+}
+
+
+@pytest.mark.parametrize("case", list(TILE_CASES))
+def test_vertex_tile_paths(md, case):
+    """Dense fluids stage most tiles' neighbour regions in LDS; dilute or tiny
+    boxes fall back to global gathers; both give the oracle's forces."""
+    name, over, expect = TILE_CASES[case]
+    w = WORKLOADS[name].with_(**over)
+    s = accepted_state(w, 9)
+    say(f"[tiles] {case}")
+    g = gpu_system(md, w, s)
+    st = g.stats()
+    if expect == "staged":  # small boxes: tiles spanning most of a row use gathers
+        assert st["tiles_staged"] >= st["tiles_total"] // 2
+    else:
+        assert st["tiles_staged"] < st["tiles_total"]
+    g.forces("vertex")
+    F, _, _, A = oracle.lj_forces(s.x, s.box, oracle.LJ(w.eps, w.sigma, w.rcut), with_abs=True)
+    assert cond_rel_err(g.get_state()["f"], F, A) <= 1e-10
+
+
 def test_vertex_equals_edge_many_calls(md):
     """Both decompositions give the same forces; repeated edge calls differ
     only at rounding level (atomic order)."""
