@@ -25,7 +25,7 @@ struct Layout {
     // workspace offsets
     uint64_t xbuild, tpos, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
         ncount, hcount, hstart, hj, chunk_row, bsum, epart, wpart, kpart, red, ctrl, tile_seg,
-        tile_nseg, tile_chunk, tile_nchunk;
+        tile_nseg, tile_chunk, tile_nchunk, tile_row0;
     int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
     long long max_half = 0;
 };
@@ -119,11 +119,12 @@ Layout layout(const md_params& p) {
     L.hstart = take(cur, 4 * (n + 1));
     L.hj = take(cur, 4 * (uint64_t)L.max_half);
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
-    L.bsum = take(cur, 4 * (uint64_t)L.nblk);
+    L.bsum = take(cur, 4 * (uint64_t)std::max(L.nblk, L.ntiles));  // per-tile half totals
     L.tile_seg = take(cur, 16 * (uint64_t)L.ntiles * md::kSegMax);
     L.tile_nseg = take(cur, 4 * (uint64_t)L.ntiles);
     L.tile_chunk = take(cur, 16 * (uint64_t)L.ntiles * md::kChunkMax);
     L.tile_nchunk = take(cur, 4 * (uint64_t)L.ntiles);
+    L.tile_row0 = take(cur, 4 * (uint64_t)L.ntiles);
     L.epart = take(cur, 8 * n);
     L.wpart = take(cur, 8 * n);
     L.kpart = take(cur, 8 * n);
@@ -292,6 +293,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.tile_nseg = (int*)(W + L.tile_nseg);
     y.tile_chunk = (int4*)(W + L.tile_chunk);
     y.tile_nchunk = (int*)(W + L.tile_nchunk);
+    y.tile_row0 = (int*)(W + L.tile_row0);
     y.epart = (double*)(W + L.epart);
     y.wpart = (double*)(W + L.wpart);
     y.kpart = (double*)(W + L.kpart);

@@ -19,7 +19,7 @@ constexpr int kScanThreads = 1024;
 // back to global gathers.
 constexpr int kTile = 64;
 constexpr int kTileTpp = kBlock / kTile;  // lanes per particle in the tiled pass
-constexpr int kSegMax = 32;
+constexpr int kSegMax = 36;
 constexpr int kChunkMax = 96;
 constexpr int kLdsCapMax = 4096;  // particles per tile region (3 doubles each)
 
@@ -104,6 +104,7 @@ struct Sys {
     int* tile_nseg;  // segments of the tile, or -1 for global gathers
     int4* tile_chunk;  // [ntiles * kChunkMax]: segments cut into runs of <= kWave slots
     int* tile_nchunk;
+    int* tile_row0;  // first home row (z * nc + y) of the tile
     double* epart;   // per-particle potential energy
     double* wpart;   // per-particle virial
     double* kpart;   // per-particle kinetic energy

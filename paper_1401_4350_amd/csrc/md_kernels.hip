@@ -298,22 +298,26 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(Sys s) {
     s.order[s.cstart[s.cell[p]] + s.rank[p]] = p;
 }
 
-// One thread per cell: order the cell's members by original id, so that the
-// slot order (and every sum over a list) does not depend on atomic timing.
+// One wavefront per cell puts the cell's members (scattered in atomic order)
+// in ascending order of their previous slot, so the slot order, and every sum
+// over a list, does not depend on atomic timing.  A member's rank is the
+// number of members with a smaller previous slot, counted with lane reads
+// over the cell (64 members at a time).  The ordered slots go to s.rank.
 __global__ __launch_bounds__(kBlock) void k_cell_sort(Sys s) {
     if (!s.ctrl->rebuild) return;
-    int c = blockIdx.x * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int c = (blockIdx.x * kBlock + threadIdx.x) / kWave;
     if (c >= s.ncell) return;
-    int b = s.cstart[c], e = s.cstart[c + 1];
-    for (int k = b + 1; k < e; k++) {
-        int p = s.order[k];
-        int key = s.id[p];
-        int m = k - 1;
-        while (m >= b && s.id[s.order[m]] > key) {
-            s.order[m + 1] = s.order[m];
-            m--;
+    const int b = s.cstart[c], m = s.cstart[c + 1] - b;
+    for (int k0 = 0; k0 < m; k0 += kWave) {
+        int p = k0 + lane < m ? s.order[b + k0 + lane] : INT_MAX;
+        int rank = 0;
+        for (int k1 = 0; k1 < m; k1 += kWave) {
+            int o = k1 + lane < m ? s.order[b + k1 + lane] : INT_MAX;
+            int lim = min(kWave, m - k1);
+            for (int l = 0; l < lim; l++) rank += __builtin_amdgcn_readlane(o, l) < p;
         }
-        s.order[m + 1] = p;
+        if (k0 + lane < m) s.rank[b + rank] = p;
     }
 }
 
@@ -321,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Sys s) {
     if (!s.ctrl->rebuild) return;
     int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= s.n) return;
-    int p = s.order[k];
+    int p = s.rank[k];  // previous slot of the particle that takes slot k
     double4 x = s.pos[p];
     s.tpos[k] = make_double4(wrap_box(x.x, s.box), wrap_box(x.y, s.box), wrap_box(x.z, s.box), 0.0);
     s.tvel[k] = s.vel[p];
@@ -333,11 +337,13 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Sys s) {
 }
 
 // ---------------------------------------------------------------------------
-// Tile regions for the LDS-staged vertex pass (one thread per tile of kTile
-// consecutive slots).  The tile's home cells form a contiguous run of cell
-// ids; their 27-cell neighbourhoods are, row by row, x-intervals of cells,
-// i.e. contiguous slot ranges.  The ranges are sorted and merged into at most
-// kSegMax disjoint segments whose concatenation is the tile's LDS image.
+// Tile regions (one thread per tile of kTile consecutive slots).  The tile's
+// home cells are a run of cell ids over at most two rows of cells; the 27-cell
+// neighbourhood of a row run is, for each of the 9 surrounding rows, an
+// x-interval of cells, i.e. a contiguous slot range, split in two where it
+// crosses the periodic boundary.  Each range is recorded with the periodic
+// image that places it next to the home cells, so the LDS copy can carry the
+// image.  Tiles over more rows, or spanning a whole row, use global gathers.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ int cell_of_slot(const int* cstart, int ncell, int slot) {
@@ -350,116 +356,79 @@ __device__ __forceinline__ int cell_of_slot(const int* cstart, int ncell, int sl
     return lo;
 }
 
-constexpr int kIvMax = 72;
-constexpr int kHomeMax = 24;
-
 __global__ __launch_bounds__(kBlock) void k_tiles(Sys s) {
     if (!s.ctrl->rebuild) return;
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= s.ntiles) return;
-    int nc = s.nc;
-    if (s.pot != 0 || nc < 3) {
+    const int nc = s.nc;
+    if (nc < 3) {
         s.tile_nseg[t] = -1;
         return;
     }
-    int a = t * kTile;
-    int b = min(a + kTile, s.n) - 1;
-    int c0 = cell_of_slot(s.cstart, s.ncell, a);
-    int c1 = cell_of_slot(s.cstart, s.ncell, b);
-    if (c1 - c0 + 1 > kHomeMax) {
-        s.tile_nseg[t] = -1;
-        return;
-    }
-    // intervals: (slot begin, slot end, periodic image code, 0); the image is
-    // the shift that brings the cells next to the tile's home cells, so the
-    // LDS copy can be stored already shifted
-    int4 iv[kIvMax];
-    int niv = 0;
-    bool over = false;
-    auto add = [&](int row, int lo, int hi, int code) {
+    const int a = t * kTile;
+    const int b = min(a + kTile, s.n) - 1;
+    const int c0 = cell_of_slot(s.cstart, s.ncell, a);
+    const int c1 = cell_of_slot(s.cstart, s.ncell, b);
+    const int r0 = c0 / nc, r1 = c1 / nc;
+    // Segment slots are fixed: two per (home row, dz, dy), in loop order, the
+    // second one empty unless the x-interval wraps; the list build finds a
+    // cell's segment by index instead of searching.
+    int4* seg = s.tile_seg + (size_t)t * kSegMax;
+    int nseg = 0, base = 0;
+    bool ok = r1 - r0 <= 1;
+    auto emit = [&](int row, int lo, int hi, int code) {
         int b0 = s.cstart[row * nc + lo], b1 = s.cstart[row * nc + hi + 1];
-        if (b1 <= b0) return;
-        if (niv == kIvMax) {
-            over = true;
-            return;
-        }
-        iv[niv++] = make_int4(b0, b1, code, 0);
+        if (base + (b1 - b0) > s.lds_cap) ok = false;
+        seg[nseg++] = make_int4(b0, b1, base, code);
+        base += b1 - b0;
     };
+    auto none = [&]() { seg[nseg++] = make_int4(0, 0, base, -1); };
     auto wrapc = [&](int v) { return v < 0 ? 0 : (v >= nc ? 2 : 1); };  // shift -L, 0, +L
-    int r0 = c0 / nc, r1 = c1 / nc;
-    for (int r = r0; r <= r1 && !over; r++) {
+    for (int r = r0; r <= r1 && ok; r++) {
         int xa = r == r0 ? c0 % nc : 0;
         int xb = r == r1 ? c1 % nc : nc - 1;
+        if (xb - xa + 3 > nc) {  // would need one row through two x images
+            ok = false;
+            break;
+        }
         int y = r % nc, z = r / nc;
-        for (int dz = -1; dz <= 1; dz++)
-            for (int dy = -1; dy <= 1; dy++) {
+        for (int dz = -1; dz <= 1 && ok; dz++)
+            for (int dy = -1; dy <= 1 && ok; dy++) {
                 int rr = ((z + dz + nc) % nc) * nc + (y + dy + nc) % nc;
                 int yz = wrapc(y + dy) << 2 | wrapc(z + dz) << 4;
                 int lo = xa - 1, hi = xb + 1;
-                if (hi - lo + 1 >= nc) {
-                    over = true;  // a full row seen through two x images
-                } else if (lo < 0) {
-                    add(rr, lo + nc, nc - 1, yz | 0);
-                    add(rr, 0, hi, yz | 1);
+                if (lo < 0) {
+                    emit(rr, lo + nc, nc - 1, yz | 0);
+                    emit(rr, 0, hi, yz | 1);
                 } else if (hi >= nc) {
-                    add(rr, lo, nc - 1, yz | 1);
-                    add(rr, 0, hi - nc, yz | 2);
+                    emit(rr, lo, nc - 1, yz | 1);
+                    emit(rr, 0, hi - nc, yz | 2);
                 } else {
-                    add(rr, lo, hi, yz | 1);
+                    emit(rr, lo, hi, yz | 1);
+                    none();
                 }
             }
     }
-    if (over) {
+    static_assert(kSegMax >= 36, "two home rows x 9 neighbour rows x 2 slots");
+    // copy chunks of at most one wavefront each
+    int4* chk = s.tile_chunk + (size_t)t * kChunkMax;
+    int nchk = 0;
+    for (int q = 0; q < nseg && ok; q++) {
+        int4 g = seg[q];
+        for (int b0 = g.x; b0 < g.y; b0 += kWave) {
+            if (nchk == kChunkMax) {
+                ok = false;
+                break;
+            }
+            chk[nchk++] = make_int4(b0, min(g.y, b0 + kWave), g.z + (b0 - g.x), g.w);
+        }
+    }
+    if (!ok) {
         s.tile_nseg[t] = -1;
         return;
     }
-    // sort by (image, start); merge overlapping or touching ranges of one image
-    for (int k = 1; k < niv; k++) {
-        int4 v = iv[k];
-        int m = k - 1;
-        while (m >= 0 && (iv[m].z > v.z || (iv[m].z == v.z && iv[m].x > v.x))) {
-            iv[m + 1] = iv[m];
-            m--;
-        }
-        iv[m + 1] = v;
-    }
-    int4* seg = s.tile_seg + (size_t)t * kSegMax;
-    int nseg = 0, base = 0;
-    int cb = -1, ce = -1, cc = -1;
-    for (int k = 0; k <= niv; k++) {
-        if (k < niv && cb >= 0 && iv[k].z == cc && iv[k].x <= ce) {
-            ce = max(ce, iv[k].y);
-            continue;
-        }
-        if (cb >= 0) {
-            if (nseg == kSegMax || base + (ce - cb) > s.lds_cap) {
-                s.tile_nseg[t] = -1;
-                return;
-            }
-            seg[nseg++] = make_int4(cb, ce, base, cc);
-            base += ce - cb;
-        }
-        if (k < niv) {
-            cb = iv[k].x;
-            ce = iv[k].y;
-            cc = iv[k].z;
-        }
-    }
-    // copy chunks of at most one wavefront each (a segment split into runs of
-    // kWave slots), consumed by the fill of the force pass without searching
-    int4* chk = s.tile_chunk + (size_t)t * kChunkMax;
-    int nchk = 0;
-    for (int q = 0; q < nseg; q++) {
-        int4 g = seg[q];
-        for (int b = g.x; b < g.y; b += kWave) {
-            if (nchk == kChunkMax) {
-                s.tile_nseg[t] = -1;
-                return;
-            }
-            chk[nchk++] = make_int4(b, min(g.y, b + kWave), g.z + (b - g.x), g.w);
-        }
-    }
     s.tile_nchunk[t] = nchk;
+    s.tile_row0[t] = r0;
     s.tile_nseg[t] = nseg;
     atomicAdd(&s.ctrl->staged, 1);
 }
@@ -474,32 +443,114 @@ __device__ __forceinline__ int tile_lds_base(const int4* seg, int nseg, int cb, 
     return -1;
 }
 
-// Global slot of LDS index idx of a tile.
-__device__ __forceinline__ int tile_slot(const int4* seg, int nseg, int idx) {
-    for (int q = 0; q < nseg; q++) {
-        int4 g = seg[q];
-        if (idx >= g.z && idx < g.z + (g.y - g.x)) return g.x + (idx - g.z);
+// ---------------------------------------------------------------------------
+// Copy of a staged tile's region into LDS (list build and vertex pass).
+// Wave v takes chunks v, v + 4, ... (runs of at most 64 slots with one image
+// each) in batches of R; chunk descriptors are wave-uniform.  The loads of a
+// batch are issued by region_issue and consumed by region_store, so a caller
+// can put other loads in between: loads retire in order, so the first batch
+// is issued before slower loads and stored right after them.
+// LDS layout: three planes (x, y, z) of `plane` doubles; slot `cap` of every
+// plane is a padding particle far outside the box.
+// ---------------------------------------------------------------------------
+
+constexpr double kFar = 1.0e15;  // coordinate of the padding slot
+__device__ __forceinline__ int lds_plane(int cap) { return cap + 8; }
+
+struct RegionBatch {
+    static constexpr int R = 8;
+    double4 p[R];
+    int4 d[R];
+};
+
+__device__ __forceinline__ void region_issue(const Sys& s, const double4* src, int tile, int nchk,
+                                             int c0, RegionBatch& b) {
+    constexpr int W = kBlock / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
+#pragma unroll
+    for (int r = 0; r < RegionBatch::R; r++) {
+        int c = c0 + r * W;
+        b.d[r] = c < nchk ? chk[c] : make_int4(0, 1, 0, -1);
+        // unconditional load (lanes past the chunk end re-read its last slot)
+        b.p[r] = src[b.d[r].x + min(lane, b.d[r].y - b.d[r].x - 1)];
     }
-    return -1;
+}
+
+__device__ __forceinline__ void region_store(const Sys& s, double* lds, int plane,
+                                             const RegionBatch& b) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int r = 0; r < RegionBatch::R; r++) {
+        const int4 d = b.d[r];
+        if (d.w >= 0 && lane < d.y - d.x) {
+            int m = d.z + lane;
+            // the chunk's periodic image is added on the way in
+            lds[m] = b.p[r].x + (double)((d.w & 3) - 1) * s.box;
+            lds[plane + m] = b.p[r].y + (double)(((d.w >> 2) & 3) - 1) * s.box;
+            lds[2 * plane + m] = b.p[r].z + (double)(((d.w >> 4) & 3) - 1) * s.box;
+        }
+    }
+}
+
+// Remaining batches, padding slot and the workgroup barrier.
+__device__ __forceinline__ void region_finish(const Sys& s, const double4* src, double* lds,
+                                              int cap, int tile, int nchk, int wv,
+                                              RegionBatch& rb) {
+    constexpr int W = kBlock / kWave;
+    const int plane = lds_plane(cap);
+    for (int c0 = wv + W * RegionBatch::R; c0 < nchk; c0 += W * RegionBatch::R) {
+        region_issue(s, src, tile, nchk, c0, rb);
+        region_store(s, lds, plane, rb);
+    }
+    if (threadIdx.x == 0) {
+        lds[cap] = kFar;
+        lds[plane + cap] = kFar;
+        lds[2 * plane + cap] = kFar;
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// Verlet-list build.  One thread per particle (slot i) scans the 27 cells
-// around its own (all cells of a dimension when fewer than three fit) and
-// keeps every j != i with r_ij^2 < r_v^2 in FP64.  It also moves its particle
-// record from the reorder buffer back into the state and stores the build
-// reference position.  Per-block totals of the half-list lengths feed the
-// half-list offsets.
+// Verlet-list build: one workgroup per tile, four lanes per particle.  The
+// four lanes of particle i scan each of its 27 neighbour cells four
+// candidates at a time (positions from the tile's LDS image when staged, in
+// FP64, from the global reorder buffer otherwise) and keep every j != i with
+// r_ij^2 < r_v^2.  Accepted candidates are compacted into i's list with a
+// wavefront ballot, so the list order (cell order, then slot) is fixed.
+// Staged entries index the LDS image; the others are slots.  The build also
+// moves the particle records from the reorder buffer back into the state and
+// stores the build reference positions; per-tile totals of the half-list
+// lengths (entries with j > i) feed the half-list offsets.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_build(Sys s) {
+__global__ __launch_bounds__(kBlock) void k_build(Sys s, int unused) {
     if (!s.ctrl->rebuild) return;
+    extern __shared__ double lds[];
     __shared__ int red[kBlock / kWave];
-    int lb = xcd_remap(blockIdx.x, gridDim.x);
-    int i = lb * kBlock + threadIdx.x;
-    int half = 0;
-    if (i < s.n) {
-        double4 xi = s.tpos[i];
+    constexpr int TPP = kTileTpp;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = tile * kTile + threadIdx.x / TPP;
+    const int q = threadIdx.x % TPP;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gshift = lane & ~(TPP - 1);  // first lane of this particle's group
+    const bool act = i < s.n;
+    const int ii = act ? i : s.n - 1;
+    const int nseg = s.tile_nseg[tile];
+    const int row0 = nseg >= 0 ? s.tile_row0[tile] : 0;
+    const int4* seg = s.tile_seg + (size_t)tile * kSegMax;
+    const int cap = s.lds_cap;
+    const int plane = lds_plane(cap);
+    if (nseg >= 0) {
+        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+        const int nchk = s.tile_nchunk[tile];
+        RegionBatch rb;
+        region_issue(s, s.tpos, tile, nchk, wv, rb);
+        region_store(s, lds, plane, rb);
+        region_finish(s, s.tpos, lds, cap, tile, nchk, wv, rb);
+    }
+    const double4 xi = s.tpos[ii];
+    if (act && q == 0) {
         s.pos[i] = xi;
         s.xbuild[i] = xi;
         s.vel[i] = s.tvel[i];
@@ -508,85 +559,107 @@ __global__ __launch_bounds__(kBlock) void k_build(Sys s) {
             s.quat[i] = s.tquat[i];
             s.angm[i] = s.tangm[i];
         }
-        int nc = s.nc;
-        int cx = cell_coord(xi.x, s.cell_inv, nc);
-        int cy = cell_coord(xi.y, s.cell_inv, nc);
-        int cz = cell_coord(xi.z, s.cell_inv, nc);
-        int span = nc >= 3 ? 3 : nc;   // distinct cells per dimension
-        int lo = nc >= 3 ? -1 : 0;
-        int count = 0;
-        // staged tile: entries index the tile's LDS image instead of slots
-        const int tile = i / kTile;
-        const int nseg = s.tile_nseg[tile];
-        const int4* seg = s.tile_seg + (size_t)tile * kSegMax;
-        for (int dz = 0; dz < span; dz++) {
-            int az = cz + lo + dz;
-            int wz = az < 0 ? 0 : (az >= nc ? 2 : 1);  // image of the cell row
-            az = az < 0 ? az + nc : (az >= nc ? az - nc : az);
-            for (int dy = 0; dy < span; dy++) {
-                int ay = cy + lo + dy;
-                int wy = ay < 0 ? 0 : (ay >= nc ? 2 : 1);
-                ay = ay < 0 ? ay + nc : (ay >= nc ? ay - nc : ay);
-                for (int dx = 0; dx < span; dx++) {
-                    int ax = cx + lo + dx;
-                    int wx = ax < 0 ? 0 : (ax >= nc ? 2 : 1);
-                    ax = ax < 0 ? ax + nc : (ax >= nc ? ax - nc : ax);
-                    int c = (az * nc + ay) * nc + ax;
-                    int e = s.cstart[c + 1];
-                    int cb = s.cstart[c];
-                    int rel = 0;  // entry value = j - rel
-                    if (nseg >= 0 && cb < e) {
-                        int base = tile_lds_base(seg, nseg, cb, wx | wy << 2 | wz << 4);
-                        if (base < 0) atomicOr(&s.ctrl->overflow, 2);  // region misses a cell
-                        rel = cb - base;
-                    }
-                    for (int j = cb; j < e; j++) {
-                        if (j == i) continue;
-                        double4 xj = s.tpos[j];
-                        double ex = xj.x - xi.x, ey = xj.y - xi.y, ez = xj.z - xi.z;
-                        double ddx = wrap_delta(ex, s.box, s.inv_box);
-                        double ddy = wrap_delta(ey, s.box, s.inv_box);
-                        double ddz = wrap_delta(ez, s.box, s.inv_box);
-                        double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                        if (r2 < s.rv2) {
-                            if (count < s.cap) {
-                                int code = image_code(ex, s.inv_box) |
-                                           image_code(ey, s.inv_box) << 2 |
-                                           image_code(ez, s.inv_box) << 4;
-                                list_row_w(s, i)[list_off(count)] = (j - rel) | code << kSlotBits;
-                                half += (j > i);
-                            }
-                            count++;
+    }
+    const int nc = s.nc;
+    const int cx = cell_coord(xi.x, s.cell_inv, nc);
+    const int cy = cell_coord(xi.y, s.cell_inv, nc);
+    const int cz = cell_coord(xi.z, s.cell_inv, nc);
+    const int span = nc >= 3 ? 3 : nc;  // distinct cells per dimension
+    const int lo = nc >= 3 ? -1 : 0;
+    int* row = list_row_w(s, ii);
+    int count = 0, half = 0;
+    for (int dz = 0; dz < span; dz++) {
+        int az = cz + lo + dz;
+        int wz = az < 0 ? 0 : (az >= nc ? 2 : 1);  // image of the cell row
+        az = az < 0 ? az + nc : (az >= nc ? az - nc : az);
+        for (int dy = 0; dy < span; dy++) {
+            int ay = cy + lo + dy;
+            int wy = ay < 0 ? 0 : (ay >= nc ? 2 : 1);
+            ay = ay < 0 ? ay + nc : (ay >= nc ? ay - nc : ay);
+            for (int dx = 0; dx < span; dx++) {
+                int ax = cx + lo + dx;
+                int wx = ax < 0 ? 0 : (ax >= nc ? 2 : 1);
+                ax = ax < 0 ? ax + nc : (ax >= nc ? ax - nc : ax);
+                const int c = (az * nc + ay) * nc + ax;
+                const int cb = act ? s.cstart[c] : 0;
+                const int ce = act ? s.cstart[c + 1] : 0;
+                const int code = wx | wy << 2 | wz << 4;
+                int base = -1;
+                if (nseg >= 0 && cb < ce) {
+                    // the two fixed segment slots of (home row, dz, dy)
+                    const int hr = cz * nc + cy - row0;
+                    const int4* sg = seg + ((hr * 3 + dz) * 3 + dy) * 2;
+                    base = (hr == 0 || hr == 1) ? tile_lds_base(sg, 2, cb, code) : -1;
+                    if (base < 0) atomicOr(&s.ctrl->overflow, 2);  // region misses a cell
+                }
+                for (int j0 = cb; j0 < ce; j0 += TPP) {
+                    const int j = j0 + q;
+                    bool cand = j < ce && j != i;
+                    double r2 = 1e300;
+                    int ent = 0;
+                    if (cand) {
+                        if (nseg >= 0) {
+                            int m = max(base, 0) + (j - cb);
+                            double ex = lds[m] - xi.x, ey = lds[plane + m] - xi.y,
+                                   ez = lds[2 * plane + m] - xi.z;
+                            r2 = ex * ex + ey * ey + ez * ez;
+                            ent = m | code << kSlotBits;
+                        } else {
+                            double4 xj = s.tpos[j];
+                            double ex = xj.x - xi.x, ey = xj.y - xi.y, ez = xj.z - xi.z;
+                            double ddx = wrap_delta(ex, s.box, s.inv_box);
+                            double ddy = wrap_delta(ey, s.box, s.inv_box);
+                            double ddz = wrap_delta(ez, s.box, s.inv_box);
+                            r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                            ent = j | (image_code(ex, s.inv_box) | image_code(ey, s.inv_box) << 2 |
+                                       image_code(ez, s.inv_box) << 4)
+                                          << kSlotBits;
                         }
                     }
+                    const bool keep = cand && r2 < s.rv2;
+                    const unsigned long long bal = __ballot(keep);
+                    const unsigned grp = (unsigned)(bal >> gshift) & ((1u << TPP) - 1);
+                    const unsigned balh = (unsigned)(__ballot(keep && j > i) >> gshift) &
+                                          ((1u << TPP) - 1);
+                    const int k = count + __builtin_popcount(grp & ((1u << q) - 1));
+                    if (keep && k < s.cap) row[list_off(k)] = ent;
+                    // half entries among the stored ones (k < cap)
+                    for (int l = 0; l < TPP; l++)
+                        if ((balh >> l) & 1) {
+                            int kl = count + __builtin_popcount(grp & ((1u << l) - 1));
+                            half += kl < s.cap;
+                        }
+                    count += __builtin_popcount(grp);
                 }
             }
         }
+    }
+    if (act && q == 0) {
         s.ncount[i] = count < s.cap ? count : s.cap;
         s.hcount[i] = half;
         if (count > s.cap) atomicOr(&s.ctrl->overflow, 1);
         atomicMax(&s.ctrl->max_count, count);
     }
-    // block total of half-list lengths
-    int v = half;
+    // tile total of half-list lengths (one lane per particle contributes)
+    int v = act && q == 0 ? half : 0;
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off);
-    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    if (lane == 0) red[threadIdx.x / kWave] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         int t = 0;
         for (int w = 0; w < kBlock / kWave; w++) t += red[w];
-        s.bsum[lb] = t;
+        s.bsum[tile] = t;
     }
 }
 
-// One workgroup: exclusive scan of the per-block half totals.
+// One workgroup: exclusive scan of the per-tile half totals.
 __global__ __launch_bounds__(kScanThreads) void k_half_scan(Sys s) {
     if (!s.ctrl->rebuild) return;
     __shared__ long long sh[kScanThreads];
     int t = threadIdx.x;
-    int per = (s.nblk + kScanThreads - 1) / kScanThreads;
+    int per = (s.ntiles + kScanThreads - 1) / kScanThreads;
     int b = t * per;
-    int e = min(b + per, s.nblk);
+    int e = min(b + per, s.ntiles);
     long long sum = 0;
     for (int k = b; k < e; k++) sum += s.bsum[k];
     sh[t] = sum;
@@ -611,46 +684,75 @@ __global__ __launch_bounds__(kScanThreads) void k_half_scan(Sys s) {
     }
 }
 
-// Same blocking as k_build: block-local exclusive scan of the half lengths plus
-// the block offset gives each row's start; the row then copies its j > i
-// entries into the CSR half list and records the chunk heads (first row of
-// every 64-entry chunk) that the edge kernel uses to find its rows.
+// Half list (edge pass): one workgroup per tile, four lanes per particle.
+// Row starts are the tile offset plus a prefix over the tile's particles; a
+// staged tile first maps its LDS indices back to slots (in LDS); each
+// particle's lanes walk its full list and keep the entries with j > i,
+// compacted with a ballot (list order is kept).  Records the chunk heads
+// (first row of every 64-entry chunk) that the edge pass uses.
 __global__ __launch_bounds__(kBlock) void k_half_fill(Sys s) {
     if (!s.ctrl->rebuild) return;
-    __shared__ int sh[kBlock];
-    int lb = xcd_remap(blockIdx.x, gridDim.x);
-    int t = threadIdx.x;
-    int i = lb * kBlock + t;
-    int h = i < s.n ? s.hcount[i] : 0;
-    sh[t] = h;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        int v = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
-    }
-    if (i >= s.n) return;
-    long long start = (long long)s.bsum[lb] + sh[t] - h;
-    long long cap = s.max_half;
-    if (start > cap) start = cap;
-    s.hstart[i] = (int)start;
-    long long end = start + h;
-    if (end > cap) end = cap;
-    if (i == s.n - 1) s.hstart[s.n] = (int)end;
-    long long k = start;
-    int cnt = s.ncount[i];
-    const int tile = i / kTile;
+    extern __shared__ int map[];
+    __shared__ int hpre[kTile];
+    constexpr int TPP = kTileTpp;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int i = tile * kTile + threadIdx.x / TPP;
+    const int q = threadIdx.x % TPP;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int gshift = lane & ~(TPP - 1);
+    const bool act = i < s.n;
     const int nseg = s.tile_nseg[tile];
-    const int4* seg = s.tile_seg + (size_t)tile * kSegMax;
-    for (int m = 0; m < cnt && k < end; m++) {
-        int ent = list_row(s, i)[list_off(m)];
-        int j = entry_slot(ent);
-        if (nseg >= 0) j = tile_slot(seg, nseg, j);  // tile-relative -> slot
-        if (j > i) s.hj[k++] = j | (ent & ~kSlotMask);
+    if (nseg >= 0) {
+        const int nchk = s.tile_nchunk[tile];
+        const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
+        for (int c = threadIdx.x / kWave; c < nchk; c += kBlock / kWave) {
+            int4 d = chk[c];
+            if (lane < d.y - d.x) map[d.z + lane] = d.x + lane;
+        }
     }
-    for (long long c0 = (start + kWave - 1) / kWave * kWave; c0 < end; c0 += kWave)
-        s.chunk_row[c0 / kWave] = i;
+    if (threadIdx.x < kTile) {
+        int ip = tile * kTile + threadIdx.x;
+        hpre[threadIdx.x] = ip < s.n ? s.hcount[ip] : 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // exclusive prefix over the tile's 64 particles
+        int run = 0;
+        for (int p = 0; p < kTile; p++) {
+            int h = hpre[p];
+            hpre[p] = run;
+            run += h;
+        }
+    }
+    __syncthreads();
+    const long long capl = s.max_half;
+    long long start = (long long)s.bsum[tile] + hpre[threadIdx.x / TPP];
+    if (start > capl) start = capl;
+    const int h = act ? s.hcount[i] : 0;
+    long long end = start + h;
+    if (end > capl) end = capl;
+    if (act && q == 0) {
+        s.hstart[i] = (int)start;
+        if (i == s.n - 1) s.hstart[s.n] = (int)end;
+        for (long long c0 = (start + kWave - 1) / kWave * kWave; c0 < end; c0 += kWave)
+            s.chunk_row[c0 / kWave] = i;
+    }
+    const int cnt = act ? s.ncount[i] : 0;
+    const int* row = list_row(s, act ? i : 0);
+    int mine = cnt > q ? (cnt - q + TPP - 1) / TPP : 0;
+    int mmax = mine;
+    for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
+    long long k = start;
+    for (int m = 0; m < mmax; m++) {
+        bool ok = m < mine;
+        int ent = ok ? row[list_off(q + m * TPP)] : 0;
+        int j = entry_slot(ent);
+        if (ok && nseg >= 0) j = map[j];  // LDS index -> slot
+        const bool keep = ok && j > i;
+        const unsigned grp = (unsigned)(__ballot(keep) >> gshift) & ((1u << TPP) - 1);
+        const long long kk = k + __builtin_popcount(grp & ((1u << q) - 1));
+        if (keep && kk < end) s.hj[kk] = j | (ent & ~kSlotMask);
+        k += __builtin_popcount(grp);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -775,54 +877,6 @@ __device__ __forceinline__ void lj_walk_global(const Sys& s, int ii, int q, int 
 #define MD_VERTEX_PREFETCH 24
 #endif
 constexpr int kPrefetch = MD_VERTEX_PREFETCH;  // list entries held in registers per lane
-constexpr double kFar = 1.0e15;                // coordinate of the padding slot
-
-// LDS image of a staged tile: three planes (x, y, z) of `plane` doubles; slot
-// `cap` of every plane is a padding particle far outside the box, so padded
-// list entries give r^2 >> r_c^2 and an exact zero.
-__device__ __forceinline__ int lds_plane(int cap) { return cap + 8; }
-
-// Copy of a staged tile's region into LDS.  Wave v takes chunks v, v + 4, ...
-// (runs of at most 64 slots with one image each, from the list build) in
-// batches of R; chunk descriptors are wave-uniform.  The loads of a batch are
-// issued by region_issue and consumed by region_store, so the caller can put
-// other loads in between: loads retire in order, so the first batch is issued
-// before the (slower) list prefetch and stored right after it.
-struct RegionBatch {
-    static constexpr int R = 8;
-    double4 p[R];
-    int4 d[R];
-};
-
-__device__ __forceinline__ void region_issue(const Sys& s, int tile, int nchk, int c0,
-                                             RegionBatch& b) {
-    constexpr int W = kBlock / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
-#pragma unroll
-    for (int r = 0; r < RegionBatch::R; r++) {
-        int c = c0 + r * W;
-        b.d[r] = c < nchk ? chk[c] : make_int4(0, 1, 0, -1);
-        // unconditional load (lanes past the chunk end re-read its last slot)
-        b.p[r] = s.pos[b.d[r].x + min(lane, b.d[r].y - b.d[r].x - 1)];
-    }
-}
-
-__device__ __forceinline__ void region_store(const Sys& s, double* lds, int plane,
-                                             const RegionBatch& b) {
-    const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-    for (int r = 0; r < RegionBatch::R; r++) {
-        const int4 d = b.d[r];
-        if (d.w >= 0 && lane < d.y - d.x) {
-            int m = d.z + lane;
-            // the chunk's periodic image is added on the way in
-            lds[m] = b.p[r].x + (double)((d.w & 3) - 1) * s.box;
-            lds[plane + m] = b.p[r].y + (double)(((d.w >> 2) & 3) - 1) * s.box;
-            lds[2 * plane + m] = b.p[r].z + (double)(((d.w >> 4) & 3) - 1) * s.box;
-        }
-    }
-}
 
 // Branch-free LJ term from an LDS image that already carries the periodic
 // image.  The cut-off selects a 0/1 factor, so every lane runs the same
@@ -892,44 +946,45 @@ __global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) {
         for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
         mmax = __builtin_amdgcn_readfirstlane(mmax);
         // region copy, first batch: issued before the list prefetch
-        constexpr int W = kBlock / kWave;
         const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
         const int nchk = s.tile_nchunk[tile];
         RegionBatch rb;
-        region_issue(s, tile, nchk, wv, rb);
-        // every lane issues all E loads (past its list end it re-reads its own
-        // first entry), so no load sits behind a branch and all are in flight
-        int en[E];
+        region_issue(s, s.pos, tile, nchk, wv, rb);
+        // every lane issues all E loads of a block (past its list end it
+        // re-reads its own first entry), so no load sits behind a branch
+        auto load_block = [&](int m0, int (&en)[E]) {
 #pragma unroll
-        for (int m = 0; m < E; m++) {
-            bool ok = m < mine;
-            int v = __builtin_nontemporal_load(nb + list_off(ok ? q + m * TPP : q));
-            // past the end: all slot bits set, clamped to the padding slot; the
-            // value depends on the load either way, so it is never skipped
-            en[m] = min(entry_slot(v) | (ok ? 0 : kSlotMask), cap);
-        }
-        region_store(s, lds, plane, rb);
-        for (int c0 = wv + W * RegionBatch::R; c0 < nchk; c0 += W * RegionBatch::R) {
-            region_issue(s, tile, nchk, c0, rb);
-            region_store(s, lds, plane, rb);
-        }
-        if (threadIdx.x == 0) {  // padding particle
-            lds[cap] = kFar;
-            lds[plane + cap] = kFar;
-            lds[2 * plane + cap] = kFar;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < E; m += 4) {
-            if (m < mmax) {
-#pragma unroll
-                for (int u = 0; u < 4; u++) lj_lds_term<PREC, ENERGY>(s, lds, plane, en[m + u], xi, f, e, w);
+            for (int m = 0; m < E; m++) {
+                bool ok = m0 + m < mine;
+                int v = __builtin_nontemporal_load(nb + list_off(ok ? q + (m0 + m) * TPP : q));
+                // past the end: all slot bits set, clamped to the padding slot;
+                // the value depends on the load either way, so it is never skipped
+                en[m] = min(entry_slot(v) | (ok ? 0 : kSlotMask), cap);
             }
-        }
-        for (int m = E; m < mmax; m++) {  // lists longer than the prefetch
-            int k = cap;
-            if (m < mine) k = entry_slot(__builtin_nontemporal_load(nb + list_off(q + m * TPP)));
-            lj_lds_term<PREC, ENERGY>(s, lds, plane, k, xi, f, e, w);
+        };
+        auto eval_block = [&](int m0, const int (&en)[E]) {
+#pragma unroll
+            for (int m = 0; m < E; m += 4) {
+                if (m0 + m < mmax) {
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        lj_lds_term<PREC, ENERGY>(s, lds, plane, en[m + u], xi, f, e, w);
+                }
+            }
+        };
+        int ea[E], eb[E];
+        load_block(0, ea);
+        region_store(s, lds, plane, rb);
+        region_finish(s, s.pos, lds, cap, tile, nchk, wv, rb);
+        // long lists: blocks of E entries, the next block's loads in flight
+        // while the current one is evaluated
+        for (int m0 = 0; m0 < mmax; m0 += 2 * E) {
+            if (m0 + E < mmax) load_block(m0 + E, eb);
+            eval_block(m0, ea);
+            if (m0 + E < mmax) {
+                if (m0 + 2 * E < mmax) load_block(m0 + 2 * E, ea);
+                eval_block(m0 + E, eb);
+            }
         }
     } else {
         lj_walk_global<PREC, TPP, ENERGY>(s, ii, q, cnt, xi, f, e, w);
@@ -1327,14 +1382,17 @@ hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) 
         hipLaunchKernelGGL(k_cell_bin, grid_n(s.n), dim3(kBlock), 0, st, s);
         hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanThreads), 0, st, s);
         hipLaunchKernelGGL(k_cell_scatter, grid_n(s.n), dim3(kBlock), 0, st, s);
-        hipLaunchKernelGGL(k_cell_sort, grid_n(s.ncell), dim3(kBlock), 0, st, s);
+        hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)(((long long)s.ncell * kWave + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, s);
         hipLaunchKernelGGL(k_reorder, grid_n(s.n), dim3(kBlock), 0, st, s);
     }
     if (lists) {
         hipLaunchKernelGGL(k_tiles, grid_n(s.ntiles), dim3(kBlock), 0, st, s);
-        hipLaunchKernelGGL(k_build, dim3(s.nblk), dim3(kBlock), 0, st, s);
+        size_t sh_pos = 3 * sizeof(double) * (size_t)(s.lds_cap + 8);
+        size_t sh_map = sizeof(int) * (size_t)(s.lds_cap + 8);
+        hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), sh_pos, st, s, 0);
         hipLaunchKernelGGL(k_half_scan, dim3(1), dim3(kScanThreads), 0, st, s);
-        hipLaunchKernelGGL(k_half_fill, dim3(s.nblk), dim3(kBlock), 0, st, s);
+        hipLaunchKernelGGL(k_half_fill, dim3(s.ntiles), dim3(kBlock), sh_map, st, s);
     }
     return hipGetLastError();
 }
