@@ -297,9 +297,13 @@ static double dot(const double* a, const double* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-double or_patchy_pair(const double* xi, const double* xj, const double* qi,
-                      const double* qj, double L, const or_patchy_params* p, double* Fj,
-                      double* ti, double* tj) {
+/* fmag and timag (optional) accumulate, per component, the magnitudes of the
+ * individual terms that make up the force on j and the torque on i (the WCA
+ * term, and for every patch pair the Gaussian and the two cosine parts): the
+ * scale against which a differently rounded evaluation is judged. */
+static double patchy_pair_impl(const double* xi, const double* xj, const double* qi,
+                               const double* qj, double L, const or_patchy_params* p, double* Fj,
+                               double* ti, double* tj, double* fmag, double* timag) {
     double d[3];
     for (int c = 0; c < 3; c++) {
         d[c] = or_min_image(xj[c] - xi[c], L);
@@ -318,7 +322,10 @@ double or_patchy_pair(const double* xi, const double* xj, const double* qi,
         V += 4.0 * p->eps * (s6 * s6 - s6) + p->eps;
         /* dV/dr_vec = -24 eps [2 s^12 - s^6] / r^2 * r_vec */
         double f = 24.0 * p->eps * (2.0 * s6 * s6 - s6) / r2;
-        for (int c = 0; c < 3; c++) dVdr[c] -= f * d[c];
+        for (int c = 0; c < 3; c++) {
+            dVdr[c] -= f * d[c];
+            if (fmag) fmag[c] += fabs(f * d[c]);
+        }
     }
 
     double ui[4][3], uj[4][3];
@@ -344,6 +351,19 @@ double or_patchy_pair(const double* xi, const double* xj, const double* qi,
             double g = -p->eps_p * exp(-s2 / w2);
             double G = g * Ai * Aj;
             V += G;
+            if (fmag && timag) {
+                double v1[3], v2[3], t1[3], t2[3];
+                for (int c = 0; c < 3; c++) {
+                    fmag[c] += fabs(2.0 * G * dab[c] / w2) +
+                               fabs(g * Aj * 2.0 * ci * (ui[a][c] - ci * rhat[c]) / r) +
+                               fabs(g * Ai * 2.0 * cj * (-uj[b][c] - cj * rhat[c]) / r);
+                    v1[c] = 2.0 * p->delta * G * dab[c] / w2;
+                    v2[c] = g * Aj * 2.0 * ci * rhat[c];
+                }
+                cross(ui[a], v1, t1);
+                cross(ui[a], v2, t2);
+                for (int c = 0; c < 3; c++) timag[c] += fabs(t1[c]) + fabs(t2[c]);
+            }
             for (int c = 0; c < 3; c++) {
                 /* d/dr of g: g * (-2/w^2) d_ab; of c_i: (u_i - c_i rhat)/r;
                  * of c_j: (-u_j - c_j rhat)/r */
@@ -369,16 +389,21 @@ double or_patchy_pair(const double* xi, const double* xj, const double* qi,
     return V;
 }
 
+double or_patchy_pair(const double* xi, const double* xj, const double* qi,
+                      const double* qj, double L, const or_patchy_params* p, double* Fj,
+                      double* ti, double* tj) {
+    return patchy_pair_impl(xi, xj, qi, qj, L, p, Fj, ti, tj, NULL, NULL);
+}
+
 static void patchy_accumulate(const double* x, const double* q, int i, int j, double L,
                               const or_patchy_params* p, double* f3, double* t3,
                               double* e, double* w, double* fa, double* ta) {
     double Fj[3], ti[3], tj[3], d[3];
-    double v = or_patchy_pair(&x[3 * i], &x[3 * j], &q[4 * i], &q[4 * j], L, p, Fj, ti, tj);
+    double v = patchy_pair_impl(&x[3 * i], &x[3 * j], &q[4 * i], &q[4 * j], L, p, Fj, ti, tj,
+                                fa, ta);
     for (int c = 0; c < 3; c++) {
         f3[c] -= Fj[c];
         t3[c] += ti[c];
-        fa[c] += fabs(Fj[c]);
-        ta[c] += fabs(ti[c]);
     }
     *e += 0.5 * v;
     sep(x, i, j, L, d);

@@ -101,7 +101,9 @@ double or_patchy_pair(const double* xi, const double* xj, const double* qi,
                       double* Fj, double* ti, double* tj);
 
 /* Forces, torques, per-particle energies and virials over all pairs; Fabs and
- * Tabs (optional) get the per-component sums of term magnitudes. */
+ * Tabs (optional) get, per component, the sums of the magnitudes of all the
+ * terms (WCA, and the Gaussian and two cosine parts of every patch pair) that
+ * make up the force and the torque. */
 void or_patchy_forces(int n, const double* x, const double* q, double L,
                       const or_patchy_params* p, int use_cells, double* F,
                       double* T, double* e, double* w, double* Fabs, double* Tabs);

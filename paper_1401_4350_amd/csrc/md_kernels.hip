@@ -147,67 +147,84 @@ __device__ __forceinline__ double exp_r(double a) { return exp(a); }
 // d = x_j - x_i (minimum image), r2 = |d|^2 < r_cut^2.  Outputs the force on j
 // (fj, the force on i is -fj), the torques on i and j, and the pair energy.
 // Torques come from the patch-vector gradients: tau = sum_a u_a x (-dV/du_a).
+// The geometry (separation, patch directions, patch-patch offsets d_ab) and
+// the WCA core are FP64 in every precision; R is the type of the Gaussian,
+// the angular products and the gradient assembly of each patch pair.  (The
+// force of a bonded pair is sensitive to its geometry: rounding the patch
+// directions or the WCA factor near its zero to FP32 would cost more than the
+// FP32 force budget.)
 template <typename R>
-__device__ __forceinline__ void patchy_pair(const V3<R>& d, R r2, const V3<R> ui[4],
-                                            const V3<R> uj[4], const PatchyC<R>& c,
-                                            V3<R>& fj, V3<R>& ti, V3<R>& tj, R& v) {
+__device__ __forceinline__ void patchy_pair(const V3<double>& d, double r2, const V3<double> ui[4],
+                                            const V3<double> uj[4], const Sys& s, V3<double>& fj,
+                                            V3<double>& ti, V3<double>& tj, double& v) {
+    const PatchyC<double>& c = s.p64;
     fj = {0, 0, 0};
     ti = {0, 0, 0};
     tj = {0, 0, 0};
     v = 0;
     if (r2 < c.wca2) {
-        R inv = R(1) / r2;
-        R s2 = c.sig2 * inv;
-        R s6 = s2 * s2 * s2;
+        double inv = 1.0 / r2;
+        double s2 = c.sig2 * inv;
+        double s6 = s2 * s2 * s2;
         v += c.eps4 * (s6 * s6 - s6) + c.eps;
-        R fr = c.eps24 * (R(2) * s6 * s6 - s6) * inv;
+        double fr = c.eps24 * (2.0 * s6 * s6 - s6) * inv;
         fj.x += fr * d.x;
         fj.y += fr * d.y;
         fj.z += fr * d.z;
     }
-    R rinv = R(1) / sqrt(r2);
-    V3<R> h = {d.x * rinv, d.y * rinv, d.z * rinv};
-    R ci[4], cj[4];
+    double rinv = 1.0 / sqrt(r2);
+    V3<double> h = {d.x * rinv, d.y * rinv, d.z * rinv};
+    double ci[4], cj[4];
 #pragma unroll
     for (int a = 0; a < 4; a++) {
         ci[a] = dot3(ui[a], h);
         cj[a] = -dot3(uj[a], h);
     }
+    const R delta = (R)c.delta, inv_w2 = (R)c.inv_w2, eps_p = (R)c.eps_p;
 #pragma unroll
     for (int a = 0; a < 4; a++) {
-        if (!(ci[a] > R(0))) continue;
-        R Ai = ci[a] * ci[a];
+        if (!(ci[a] > 0.0)) continue;
 #pragma unroll
         for (int b = 0; b < 4; b++) {
-            if (!(cj[b] > R(0))) continue;
-            R Aj = cj[b] * cj[b];
-            V3<R> dd = {d.x + c.delta * (uj[b].x - ui[a].x), d.y + c.delta * (uj[b].y - ui[a].y),
-                        d.z + c.delta * (uj[b].z - ui[a].z)};
-            R s2 = dot3(dd, dd);
-            if (c.rpc2 > R(0) && !(s2 < c.rpc2)) continue;
-            R g = -c.eps_p * exp_r(-s2 * c.inv_w2);
+            if (!(cj[b] > 0.0)) continue;
+            V3<double> dd64 = {d.x + c.delta * (uj[b].x - ui[a].x),
+                               d.y + c.delta * (uj[b].y - ui[a].y),
+                               d.z + c.delta * (uj[b].z - ui[a].z)};
+            double s2 = dot3(dd64, dd64);
+            if (c.rpc2 > 0.0 && !(s2 < c.rpc2)) continue;
+            // assembly in R from the FP64 geometry
+            const R cia = (R)ci[a], cjb = (R)cj[b], rinvR = (R)rinv, r = (R)(r2 * rinv);
+            const V3<R> dd = {(R)dd64.x, (R)dd64.y, (R)dd64.z};
+            const V3<R> hh = {(R)h.x, (R)h.y, (R)h.z};
+            const V3<R> ua = {(R)ui[a].x, (R)ui[a].y, (R)ui[a].z};
+            const V3<R> ub = {(R)uj[b].x, (R)uj[b].y, (R)uj[b].z};
+            R Ai = cia * cia, Aj = cjb * cjb;
+            R g = -eps_p * exp_r((R)(-s2 * c.inv_w2));
             R G = g * Ai * Aj;
-            v += G;
+            v += (double)G;
             // gradient pieces: Gaussian (along d_ab) and the two cosines
-            R kd = R(2) * G * c.inv_w2;           // -dG/d(d_ab) = -kd... see below
-            R ki = g * Aj * R(2) * ci[a] * rinv;  // d/dr through c_i
-            R kj = g * Ai * R(2) * cj[b] * rinv;  // d/dr through c_j
+            R kd = R(2) * G * inv_w2;           // Gaussian: dV/dr gets -kd d_ab
+            R ki = g * Aj * R(2) * cia * rinvR;  // through c_i
+            R kj = g * Ai * R(2) * cjb * rinvR;  // through c_j
             // dV/dr = -kd d_ab + ki (u_i - c_i h) + kj (-u_j - c_j h); F_j = -dV/dr
-            fj.x += kd * dd.x - ki * (ui[a].x - ci[a] * h.x) + kj * (uj[b].x + cj[b] * h.x);
-            fj.y += kd * dd.y - ki * (ui[a].y - ci[a] * h.y) + kj * (uj[b].y + cj[b] * h.y);
-            fj.z += kd * dd.z - ki * (ui[a].z - ci[a] * h.z) + kj * (uj[b].z + cj[b] * h.z);
+            fj.x += (double)(kd * dd.x - ki * (ua.x - cia * hh.x) + kj * (ub.x + cjb * hh.x));
+            fj.y += (double)(kd * dd.y - ki * (ua.y - cia * hh.y) + kj * (ub.y + cjb * hh.y));
+            fj.z += (double)(kd * dd.z - ki * (ua.z - cia * hh.z) + kj * (ub.z + cjb * hh.z));
             // -dV/du_i = -(delta kd d_ab + ki r h),  -dV/du_j = delta kd d_ab + kj r h
-            R r = r2 * rinv;
-            V3<R> mi = {-(c.delta * kd * dd.x + ki * r * h.x), -(c.delta * kd * dd.y + ki * r * h.y),
-                        -(c.delta * kd * dd.z + ki * r * h.z)};
-            V3<R> mj = {c.delta * kd * dd.x + kj * r * h.x, c.delta * kd * dd.y + kj * r * h.y,
-                        c.delta * kd * dd.z + kj * r * h.z};
-            ti.x += ui[a].y * mi.z - ui[a].z * mi.y;
-            ti.y += ui[a].z * mi.x - ui[a].x * mi.z;
-            ti.z += ui[a].x * mi.y - ui[a].y * mi.x;
-            tj.x += uj[b].y * mj.z - uj[b].z * mj.y;
-            tj.y += uj[b].z * mj.x - uj[b].x * mj.z;
-            tj.z += uj[b].x * mj.y - uj[b].y * mj.x;
+            V3<R> mi = {-(delta * kd * dd.x + ki * r * hh.x), -(delta * kd * dd.y + ki * r * hh.y),
+                        -(delta * kd * dd.z + ki * r * hh.z)};
+            V3<R> mj = {delta * kd * dd.x + kj * r * hh.x, delta * kd * dd.y + kj * r * hh.y,
+                        delta * kd * dd.z + kj * r * hh.z};
+            // torques: u x m with the FP64 direction (m nearly parallel to u for
+            // a bonded patch, so the cross product cancels)
+            const double mix = mi.x, miy = mi.y, miz = mi.z;
+            const double mjx = mj.x, mjy = mj.y, mjz = mj.z;
+            ti.x += ui[a].y * miz - ui[a].z * miy;
+            ti.y += ui[a].z * mix - ui[a].x * miz;
+            ti.z += ui[a].x * miy - ui[a].y * mix;
+            tj.x += uj[b].y * mjz - uj[b].z * mjy;
+            tj.y += uj[b].z * mjx - uj[b].x * mjz;
+            tj.z += uj[b].x * mjy - uj[b].y * mjx;
         }
     }
 }
@@ -361,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles(Sys s) {
     int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= s.ntiles) return;
     const int nc = s.nc;
-    if (nc < 3) {
+    if (nc < 3 || s.pot != 0) {  // the patchy pass gathers from global memory
         s.tile_nseg[t] = -1;
         return;
     }
@@ -1024,10 +1041,9 @@ __global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) {
     int i = lb * kBlock + threadIdx.x;
     if (KICK && blockIdx.x == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
     if (i >= s.n) return;
-    const PatchyC<R>& c = pick<R>(s.p64, s.p32);
     double4 xi = s.pos[i];
-    V3<R> ui[4];
-    patch_dirs<R>(s.quat[i], ui);
+    V3<double> ui[4];
+    patch_dirs<double>(s.quat[i], ui);
     int cnt = s.ncount[i];
     Acc3<PREC> f, t;
     double e = 0, w = 0;
@@ -1041,12 +1057,12 @@ __global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) {
         double dz = xj.z - xi.z + image(ent, 2, s.box);
         double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < s.rc2) {
-            V3<R> uj[4];
-            patch_dirs<R>(s.quat[j], uj);
-            V3<R> d = {(R)dx, (R)dy, (R)dz};
-            V3<R> fj, ti, tj;
-            R v;
-            patchy_pair<R>(d, (R)r2, ui, uj, c, fj, ti, tj, v);
+            V3<double> uj[4];
+            patch_dirs<double>(s.quat[j], uj);
+            V3<double> d = {dx, dy, dz};
+            V3<double> fj, ti, tj;
+            double v;
+            patchy_pair<R>(d, r2, ui, uj, s, fj, ti, tj, v);
             f.add(-fj.x, -fj.y, -fj.z);
             t.add(ti.x, ti.y, ti.z);
             if (ENERGY) {
@@ -1156,14 +1172,13 @@ __global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
                         fz = fr * (float)dz;
                     }
                 } else {
-                    const PatchyC<R>& c = pick<R>(s.p64, s.p32);
-                    V3<R> ui[4], uj[4];
-                    patch_dirs<R>(s.quat[i], ui);
-                    patch_dirs<R>(s.quat[j], uj);
-                    V3<R> d = {(R)dx, (R)dy, (R)dz};
-                    V3<R> fj, ti, tj;
-                    R v;
-                    patchy_pair<R>(d, (R)r2, ui, uj, c, fj, ti, tj, v);
+                    V3<double> ui[4], uj[4];
+                    patch_dirs<double>(s.quat[i], ui);
+                    patch_dirs<double>(s.quat[j], uj);
+                    V3<double> d = {dx, dy, dz};
+                    V3<double> fj, ti, tj;
+                    double v;
+                    patchy_pair<R>(d, r2, ui, uj, s, fj, ti, tj, v);
                     fx = fj.x;
                     fy = fj.y;
                     fz = fj.z;
