@@ -189,8 +189,95 @@ md_status md_profile_enable(md_system* s, int32_t on);
 /* Reads the sums (syncs). */
 md_status md_profile_read(md_system* s, md_profile_t* out);
 
-/* Destroy the handle (does not free the caller's buffers). */
+/* Destroy the handle (does not free the caller's buffers).  A system still
+ * admitted to a batch is retired first. */
 void md_destroy(md_system* s);
+
+/* ---------------------------------------------------------------------------
+ * Batched serving.  Many independent systems (different n, potential,
+ * density and precision) advance together: every kernel of one step runs once
+ * for the whole batch, each block serving one block's worth of one system, so
+ * small systems share the GPU instead of each paying the launch latency of a
+ * full step.  The paper times single systems only (Results section); the
+ * batch runs the same per-system arithmetic -- a system's vertex-mode
+ * trajectory is bitwise the one md_step gives it alone, and an edge-mode one
+ * differs only by the order of its atomic additions.
+ *
+ * The batch keeps a device table of per-slot descriptors and, per block class
+ * of the step, a map from grid block to (slot, block of that system).  Grids
+ * are sized once from max_systems and max_particles, so admission and
+ * retirement only rewrite the table and maps between launches.  A launch
+ * runs steps_per_launch steps (fewer when no system needs that many) as one
+ * hipGraph, captured on first use and again only when an admitted system
+ * needs a larger LDS region than the captured graph provides.
+ * ------------------------------------------------------------------------- */
+typedef struct md_batch md_batch; /* opaque handle */
+
+typedef struct {
+    int32_t max_systems;      /* slots, 1 .. 65536                                    */
+    int32_t mode;             /* md_mode of every step                                */
+    int32_t steps_per_launch; /* steps in one launch, 1 .. 4096                        */
+    int32_t use_graph;        /* 1: launch captured hipGraphs; 0: launch kernels      */
+    int64_t max_particles;    /* bound on the sum of n over admitted systems          */
+    uint64_t pool_bytes;      /* bound on the sum of the systems' state + workspace
+                                 bytes (md_query_sizes): the HBM footprint budget     */
+} md_batch_params;
+
+/* Device workspace bytes of a batch (pure host, no HIP call). */
+md_status md_batch_query_sizes(const md_batch_params* p, uint64_t* workspace_bytes);
+
+/* Create an empty batch.  d_workspace (aligned to 256 bytes, at least
+ * md_batch_query_sizes bytes) is borrowed and must outlive the handle; all
+ * work runs on hip_stream.  MD_ERR_INVALID_ARG for bad parameters,
+ * MD_ERR_BUFFER_TOO_SMALL for a short or misaligned workspace. */
+md_status md_batch_create(const md_batch_params* p, void* d_workspace, uint64_t workspace_bytes,
+                          void* hip_stream, md_batch** out);
+
+/* Admit a system for nsteps (>= 0) further steps and return its slot.  The
+ * system must have built lists (md_build_neighbors); its forces are computed
+ * with the batch's mode if not valid, and its own stream is drained.  While
+ * admitted, every single-system call on it returns MD_ERR_STATE.  Returns
+ * MD_ERR_BUFFER_TOO_SMALL, with nothing changed, when no slot is free or the
+ * system would exceed pool_bytes, max_particles or a block-class capacity;
+ * MD_ERR_STATE when it is in a batch already or has no lists.  Syncs the
+ * batch stream. */
+md_status md_batch_admit(md_batch* b, md_system* s, int64_t nsteps, int32_t* slot);
+
+/* One launch: every admitted system with steps left advances by
+ * min(steps left, k) steps, where k is steps_per_launch, or the smallest power
+ * of two covering the largest need when that is fewer.  *steps_run (may be
+ * NULL) receives k, 0 if no system had steps left.  Async. */
+md_status md_batch_step(md_batch* b, int32_t* steps_run);
+
+/* Steps the slot's system has left (host bookkeeping, no sync); -1 for a free
+ * slot. */
+md_status md_batch_steps_left(const md_batch* b, int32_t slot, int64_t* left);
+
+/* Remove the slot's system from the batch (also to cancel it early) and free
+ * the slot.  Syncs; returns the system's own device status (list overflow,
+ * non-finite forces) and leaves it usable by the single-system calls. */
+md_status md_batch_retire(md_batch* b, int32_t slot);
+
+/* Waits for the batch stream. */
+md_status md_batch_sync(md_batch* b);
+
+typedef struct {
+    int32_t active;          /* admitted systems                                     */
+    int32_t lds_cap;         /* LDS region capacity of the captured graph (slots)    */
+    int64_t particles;       /* sum of n over admitted systems                       */
+    uint64_t bytes;          /* sum of their footprints                              */
+    int64_t launches;        /* md_batch_step launches so far                        */
+    int64_t captures;        /* graphs captured so far                               */
+} md_batch_info_t;
+
+md_status md_batch_info(const md_batch* b, md_batch_info_t* out);
+
+/* Retires every admitted system and destroys the handle (not the caller's
+ * workspace). */
+void md_batch_destroy(md_batch* b);
+
+/* Description of the last error on this batch ("" if none). */
+const char* md_batch_last_error(const md_batch* b);
 
 /* Static description of a status code. */
 const char* md_status_str(int32_t status);

@@ -160,6 +160,8 @@ struct md_system {
     bool forces_valid = false;
     long long steps = 0;
     int edge_grid = 1;
+    md_batch* batch = nullptr;  // set while admitted to a batch
+    int batch_slot = -1;
     std::string err;
     // md_step phase timing (md_profile_enable)
     bool profiling = false;
@@ -182,6 +184,9 @@ struct md_system {
     md_status fail(md_status st, const std::string& msg) {
         err = msg;
         return st;
+    }
+    md_status admitted() {
+        return fail(MD_ERR_STATE, "the system is admitted to a batch; md_batch_retire it first");
     }
     md_status hip(hipError_t e, const char* where) {
         if (e == hipSuccess) return MD_OK;
@@ -302,6 +307,8 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     long long waves = (L.max_half + md::kWave - 1) / md::kWave;
     long long blocks = (waves + 3) / 4;
     s->edge_grid = (int)std::max(1LL, std::min(blocks, 4096LL));
+    y.eblk = std::min(s->edge_grid, 4 * L.ntiles);  // edge blocks when stepped in a batch
+    y.prec = p->prec;
 
     // One-time clears at creation (never inside a captured step).
     st = s->hip(hipMemsetAsync(y.ccount, 0, 4 * (size_t)L.ncell, s->stream), "clear cell counts");
@@ -319,6 +326,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
 md_status md_set_state(md_system* s, const double* x, const double* v, const double* q,
                        const double* angmom) {
     if (!s || !x || !v) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     bool patchy = s->p.pot == MD_POT_PATCHY;
     if (patchy && (!q || !angmom)) return s->fail(MD_ERR_INVALID_ARG, "patchy needs q and angmom");
     int n = s->p.n;
@@ -377,6 +385,7 @@ md_status md_set_state(md_system* s, const double* x, const double* v, const dou
 
 md_status md_build_cells(md_system* s) {
     if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     if (!s->state_set) return s->fail(MD_ERR_STATE, "md_set_state first");
     md_status r = s->hip(md::launch_set_rebuild(s->sys, s->stream), "set rebuild");
     if (r == MD_OK) r = s->hip(md::launch_rebuild(s->sys, s->stream, true, false), "cell sort");
@@ -389,6 +398,7 @@ md_status md_build_cells(md_system* s) {
 
 md_status md_build_neighbors(md_system* s) {
     if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     if (!s->cells_pending) return s->fail(MD_ERR_STATE, "md_build_cells first");
     md_status r = s->hip(md::launch_rebuild(s->sys, s->stream, false, true), "list build");
     if (r == MD_OK) r = s->hip(md::launch_clear_rebuild(s->sys, s->stream), "clear rebuild");
@@ -401,6 +411,7 @@ md_status md_build_neighbors(md_system* s) {
 
 md_status md_forces(md_system* s, int32_t mode) {
     if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     if (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE) return s->fail(MD_ERR_INVALID_ARG, "mode");
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
     md_status r = s->hip(md::launch_forces(s->sys, mode, s->p.prec, false, s->stream, s->edge_grid),
@@ -412,6 +423,7 @@ md_status md_forces(md_system* s, int32_t mode) {
 
 md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     if (nsteps < 0 || (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE))
         return s->fail(MD_ERR_INVALID_ARG, "nsteps/mode");
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
@@ -458,6 +470,7 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
 
 md_status md_profile_enable(md_system* s, int32_t on) {
     if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     s->profiling = on != 0;
     s->prof = md_profile_t{};
     return MD_OK;
@@ -465,6 +478,7 @@ md_status md_profile_enable(md_system* s, int32_t on) {
 
 md_status md_profile_read(md_system* s, md_profile_t* out) {
     if (!s || !out) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     md_status r = s->hip(hipStreamSynchronize(s->stream), "profile sync");
     if (r != MD_OK) return r;
     *out = s->prof;
@@ -473,6 +487,7 @@ md_status md_profile_read(md_system* s, md_profile_t* out) {
 
 md_status md_energy(md_system* s, double* e_kin, double* e_pot, double* virial) {
     if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
     md_status r = s->hip(md::launch_energy(s->sys, s->p.prec, s->stream), "energy");
     if (r != MD_OK) return r;
@@ -497,6 +512,7 @@ static md_status download_ids(md_system* s, std::vector<int>& id) {
 
 md_status md_particle_energies(md_system* s, double* e) {
     if (!s || !e) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
     int n = s->p.n;
     std::vector<double> h(n);
@@ -516,6 +532,7 @@ md_status md_particle_energies(md_system* s, double* e) {
 md_status md_get_state(md_system* s, double* x, double* v, double* f, double* q, double* angmom,
                        double* torque) {
     if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     if (!s->state_set) return s->fail(MD_ERR_STATE, "md_set_state first");
     bool patchy = s->p.pot == MD_POT_PATCHY;
     if (!patchy && (q || angmom || torque)) return s->fail(MD_ERR_INVALID_ARG, "LJ has no rotation");
@@ -556,6 +573,7 @@ md_status md_get_state(md_system* s, double* x, double* v, double* f, double* q,
 
 md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pairs) {
     if (!s || !n_pairs || cap < 0 || (cap > 0 && !pairs)) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
     md_status r = s->sync_check();
     if (r != MD_OK) return r;
@@ -585,6 +603,7 @@ md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pai
 
 md_status md_stats(md_system* s, md_stats_t* out) {
     if (!s || !out) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
     md_status r = s->hip(hipStreamSynchronize(s->stream), "stats sync");
     md::Ctrl c;
     if (r == MD_OK) r = s->hip(hipMemcpy(&c, s->sys.ctrl, sizeof c, hipMemcpyDeviceToHost), "ctrl");
@@ -599,10 +618,349 @@ md_status md_stats(md_system* s, md_stats_t* out) {
     return MD_OK;
 }
 
-void md_destroy(md_system* s) { delete s; }
+void md_destroy(md_system* s) {
+    if (s && s->batch) (void)md_batch_retire(s->batch, s->batch_slot);
+    delete s;
+}
 
 const char* md_status_str(int32_t status) { return status_text(status); }
 
 const char* md_last_error(const md_system* s) { return s ? s->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched serving (md_batch_*).
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct BatchLayout {
+    uint64_t tab = 0, left = 0, map[md::kNumClasses] = {}, bytes = 0;
+    int cap[md::kNumClasses] = {};
+};
+
+md_status validate_batch(const md_batch_params* p) {
+    if (!p) return MD_ERR_INVALID_ARG;
+    if (p->max_systems < 1 || p->max_systems > 65536) return MD_ERR_INVALID_ARG;
+    if (p->mode != MD_MODE_VERTEX && p->mode != MD_MODE_EDGE) return MD_ERR_INVALID_ARG;
+    if (p->steps_per_launch < 1 || p->steps_per_launch > 4096) return MD_ERR_INVALID_ARG;
+    if (p->use_graph != 0 && p->use_graph != 1) return MD_ERR_INVALID_ARG;
+    if (p->max_particles < 2 || p->max_particles > (1LL << 30)) return MD_ERR_INVALID_ARG;
+    if (p->pool_bytes == 0) return MD_ERR_INVALID_ARG;
+    return MD_OK;
+}
+
+// Grid capacity of every block class: enough for max_particles spread over
+// max_systems systems (each system rounds up once per class).
+BatchLayout batch_layout(const md_batch_params& p) {
+    BatchLayout L;
+    long long nmax = p.max_particles, smax = p.max_systems;
+    long long tiles = (nmax + md::kTile - 1) / md::kTile + smax;
+    long long c[md::kNumClasses];
+    c[md::kClsParticle] = (nmax + md::kBlock - 1) / md::kBlock + smax;
+    c[md::kClsTile] = tiles;
+    c[md::kClsTileScan] = (tiles + md::kBlock - 1) / md::kBlock + smax;
+    c[md::kClsCellSort] = nmax * 2 / (md::kBlock / md::kWave) + smax;  // up to 2 cells per particle
+    c[md::kClsSystem] = smax;
+    c[md::kClsVertex] = tiles;
+    c[md::kClsEdge] = 4 * tiles;
+    uint64_t cur = 0;
+    L.tab = take(cur, sizeof(md::Sys) * (uint64_t)smax);
+    L.left = take(cur, 4 * (uint64_t)smax);
+    for (int k = 0; k < md::kNumClasses; k++) {
+        L.cap[k] = (int)c[k];
+        L.map[k] = take(cur, sizeof(int2) * (uint64_t)c[k]);
+    }
+    L.bytes = cur;
+    return L;
+}
+
+// Host twin of the kernels' XCD re-indexing: grid block g runs on XCD g % 8;
+// hand each XCD a contiguous range of the class's block list.
+int xcd_remap_host(int g, int total) {
+    const int nx = 8;
+    int q = total / nx, r = total % nx;
+    int x = g % nx, k = g / nx;
+    return x * q + (x < r ? x : r) + k;
+}
+
+}  // namespace
+
+struct md_batch {
+    md_batch_params p;
+    BatchLayout lay;
+    hipStream_t stream = nullptr;   // caller's: uploads and launches
+    hipStream_t capture = nullptr;  // private: graph capture only
+    md::BatchDev dev{};
+    std::vector<md_system*> slot;
+    std::vector<long long> left;      // host bookkeeping of steps left
+    std::vector<long long> admitted;  // steps requested at admission
+    // staging of the device table; written only after the stream is drained
+    std::vector<md::Sys> h_tab;
+    std::vector<int> h_left;
+    std::vector<int2> h_map[md::kNumClasses];
+    int used[md::kNumClasses] = {};
+    int uploaded[md::kNumClasses] = {};  // map entries that may be non-idle on the device
+    int active = 0;
+    long long particles = 0;
+    uint64_t bytes = 0;
+    int lds_cap = 512;  // LDS region capacity the graphs are captured for
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;  // by steps per launch
+    long long launches = 0, captures = 0;
+    std::string err;
+
+    md_status fail(md_status st, const std::string& msg) {
+        err = msg;
+        return st;
+    }
+    md_status hip(hipError_t e, const char* where) {
+        if (e == hipSuccess) return MD_OK;
+        err = std::string(where) + ": " + hipGetErrorString(e);
+        return MD_ERR_HIP;
+    }
+    void drop_graphs() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
+    ~md_batch() {
+        drop_graphs();
+        if (capture) (void)hipStreamDestroy(capture);
+    }
+
+    // Rewrites the block maps and uploads table, step budgets and maps.
+    // The caller has drained the stream, so the staging buffers are free.
+    md_status upload() {
+        for (int c = 0; c < md::kNumClasses; c++) {
+            std::vector<int2> list;
+            list.reserve(used[c]);
+            for (int k = 0; k < p.max_systems; k++) {
+                if (!slot[k]) continue;
+                int nb = md::class_blocks(h_tab[k], c);
+                for (int l = 0; l < nb; l++) list.push_back(make_int2(k, l));
+            }
+            int total = (int)list.size();
+            int span = std::max(total, uploaded[c]);
+            std::vector<int2>& m = h_map[c];
+            m.assign((size_t)span, make_int2(-1, 0));
+            for (int g = 0; g < total; g++) m[g] = list[xcd_remap_host(g, total)];
+            if (span > 0) {
+                md_status r = hip(hipMemcpyAsync((void*)dev.map[c], m.data(), sizeof(int2) * (size_t)span,
+                                                 hipMemcpyHostToDevice, stream),
+                                  "upload block map");
+                if (r != MD_OK) return r;
+            }
+            uploaded[c] = total;
+        }
+        for (int k = 0; k < p.max_systems; k++) h_left[k] = slot[k] ? (int)left[k] : 0;
+        md_status r = hip(hipMemcpyAsync((void*)dev.tab, h_tab.data(), sizeof(md::Sys) * h_tab.size(),
+                                         hipMemcpyHostToDevice, stream),
+                          "upload table");
+        if (r == MD_OK)
+            r = hip(hipMemcpyAsync(dev.left, h_left.data(), 4 * h_left.size(), hipMemcpyHostToDevice,
+                                   stream),
+                    "upload budgets");
+        if (r == MD_OK) r = hip(hipStreamSynchronize(stream), "upload sync");
+        return r;
+    }
+
+    md_status graph_for(int steps, hipGraphExec_t* out) {
+        for (auto& g : graphs)
+            if (g.first == steps) {
+                *out = g.second;
+                return MD_OK;
+            }
+        hipGraph_t graph = nullptr;
+        md_status r = hip(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (r != MD_OK) return r;
+        hipError_t e = md::launch_batch_steps(dev, lay.cap, lds_cap, p.mode, steps, capture);
+        hipError_t e2 = hipStreamEndCapture(capture, &graph);
+        r = hip(e != hipSuccess ? e : e2, "capture batch step");
+        hipGraphExec_t exec = nullptr;
+        if (r == MD_OK) r = hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
+        if (graph) (void)hipGraphDestroy(graph);
+        if (r != MD_OK) return r;
+        graphs.emplace_back(steps, exec);
+        captures++;
+        *out = exec;
+        return MD_OK;
+    }
+};
+
+extern "C" {
+
+md_status md_batch_query_sizes(const md_batch_params* p, uint64_t* workspace_bytes) {
+    if (!workspace_bytes) return MD_ERR_INVALID_ARG;
+    md_status st = validate_batch(p);
+    if (st != MD_OK) return st;
+    *workspace_bytes = batch_layout(*p).bytes;
+    return MD_OK;
+}
+
+md_status md_batch_create(const md_batch_params* p, void* d_workspace, uint64_t workspace_bytes,
+                          void* hip_stream, md_batch** out) {
+    if (!out) return MD_ERR_INVALID_ARG;
+    *out = nullptr;
+    md_status st = validate_batch(p);
+    if (st != MD_OK) return st;
+    if (!d_workspace) return MD_ERR_INVALID_ARG;
+    BatchLayout L = batch_layout(*p);
+    if (workspace_bytes < L.bytes || (uintptr_t)d_workspace % kAlign) return MD_ERR_BUFFER_TOO_SMALL;
+    md_batch* b = new md_batch();
+    b->p = *p;
+    b->lay = L;
+    b->stream = (hipStream_t)hip_stream;
+    char* W = (char*)d_workspace;
+    b->dev.tab = (const md::Sys*)(W + L.tab);
+    b->dev.left = (int*)(W + L.left);
+    for (int c = 0; c < md::kNumClasses; c++) b->dev.map[c] = (const int2*)(W + L.map[c]);
+    b->dev.nslots = p->max_systems;
+    b->slot.assign(p->max_systems, nullptr);
+    b->left.assign(p->max_systems, 0);
+    b->admitted.assign(p->max_systems, 0);
+    b->h_tab.resize(p->max_systems);
+    std::memset((void*)b->h_tab.data(), 0, sizeof(md::Sys) * b->h_tab.size());
+    b->h_left.assign(p->max_systems, 0);
+    st = b->hip(hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking), "capture stream");
+    // every map entry idle, every budget zero
+    if (st == MD_OK) st = b->hip(hipMemsetAsync(d_workspace, 0, L.bytes, b->stream), "clear batch");
+    for (int c = 0; c < md::kNumClasses && st == MD_OK; c++) b->uploaded[c] = L.cap[c];
+    if (st == MD_OK) st = b->upload();
+    if (st != MD_OK) {
+        delete b;
+        return st;
+    }
+    *out = b;
+    return MD_OK;
+}
+
+md_status md_batch_admit(md_batch* b, md_system* s, int64_t nsteps, int32_t* slot) {
+    if (!b || !s || !slot || nsteps < 0 || nsteps > INT32_MAX) return MD_ERR_INVALID_ARG;
+    *slot = -1;
+    if (s->batch) return b->fail(MD_ERR_STATE, "system already admitted to a batch");
+    if (!s->lists_valid) return b->fail(MD_ERR_STATE, "system has no lists (md_build_neighbors)");
+    int k = 0;
+    while (k < b->p.max_systems && b->slot[k]) k++;
+    if (k == b->p.max_systems) return b->fail(MD_ERR_BUFFER_TOO_SMALL, "no free slot");
+    uint64_t foot = s->lay.state_bytes + s->lay.ws_bytes;
+    if (b->bytes + foot > b->p.pool_bytes)
+        return b->fail(MD_ERR_BUFFER_TOO_SMALL, "footprint exceeds the pool budget");
+    if (b->particles + s->p.n > b->p.max_particles)
+        return b->fail(MD_ERR_BUFFER_TOO_SMALL, "particles exceed max_particles");
+    for (int c = 0; c < md::kNumClasses; c++)
+        if (b->used[c] + md::class_blocks(s->sys, c) > b->lay.cap[c])
+            return b->fail(MD_ERR_BUFFER_TOO_SMALL,
+                           "block class " + std::to_string(c) + " is full");
+    if (!s->forces_valid) {
+        md_status r = md_forces(s, b->p.mode);
+        if (r != MD_OK) return b->fail(r, std::string("initial forces: ") + s->err);
+    }
+    md_status r = s->sync_check();
+    if (r != MD_OK) return b->fail(r, std::string("system: ") + s->err);
+    r = b->hip(hipStreamSynchronize(b->stream), "admit sync");
+    if (r != MD_OK) return r;
+    b->slot[k] = s;
+    b->h_tab[k] = s->sys;
+    b->left[k] = nsteps;
+    b->admitted[k] = nsteps;
+    for (int c = 0; c < md::kNumClasses; c++) b->used[c] += md::class_blocks(s->sys, c);
+    b->active++;
+    b->particles += s->p.n;
+    b->bytes += foot;
+    if (s->sys.lds_cap > b->lds_cap) {  // graphs were captured with too little LDS
+        b->lds_cap = (s->sys.lds_cap + 511) / 512 * 512;
+        b->drop_graphs();
+    }
+    s->batch = b;
+    s->batch_slot = k;
+    r = b->upload();
+    if (r != MD_OK) return r;
+    *slot = k;
+    return MD_OK;
+}
+
+md_status md_batch_step(md_batch* b, int32_t* steps_run) {
+    if (!b) return MD_ERR_INVALID_ARG;
+    if (steps_run) *steps_run = 0;
+    long long need = 0;
+    for (int k = 0; k < b->p.max_systems; k++)
+        if (b->slot[k]) need = std::max(need, b->left[k]);
+    if (need == 0) return MD_OK;
+    int steps = b->p.steps_per_launch;
+    if (need < steps) {
+        steps = 1;
+        while (steps < need) steps *= 2;
+        steps = std::min(steps, b->p.steps_per_launch);
+    }
+    md_status r;
+    if (b->p.use_graph) {
+        hipGraphExec_t exec = nullptr;
+        r = b->graph_for(steps, &exec);
+        if (r == MD_OK) r = b->hip(hipGraphLaunch(exec, b->stream), "graph launch");
+    } else {
+        r = b->hip(md::launch_batch_steps(b->dev, b->lay.cap, b->lds_cap, b->p.mode, steps, b->stream),
+                   "batch launch");
+    }
+    if (r != MD_OK) return r;
+    for (int k = 0; k < b->p.max_systems; k++)
+        if (b->slot[k]) b->left[k] -= std::min<long long>(b->left[k], steps);
+    b->launches++;
+    if (steps_run) *steps_run = steps;
+    return MD_OK;
+}
+
+md_status md_batch_steps_left(const md_batch* b, int32_t slot, int64_t* left) {
+    if (!b || !left || slot < 0 || slot >= b->p.max_systems) return MD_ERR_INVALID_ARG;
+    *left = b->slot[slot] ? b->left[slot] : -1;
+    return MD_OK;
+}
+
+md_status md_batch_retire(md_batch* b, int32_t slot) {
+    if (!b || slot < 0 || slot >= b->p.max_systems) return MD_ERR_INVALID_ARG;
+    md_system* s = b->slot[slot];
+    if (!s) return b->fail(MD_ERR_INVALID_ARG, "slot is free");
+    md_status r = b->hip(hipStreamSynchronize(b->stream), "retire sync");
+    if (r != MD_OK) return r;
+    for (int c = 0; c < md::kNumClasses; c++) b->used[c] -= md::class_blocks(s->sys, c);
+    b->active--;
+    b->particles -= s->p.n;
+    b->bytes -= s->lay.state_bytes + s->lay.ws_bytes;
+    s->steps += b->admitted[slot] - b->left[slot];
+    b->slot[slot] = nullptr;
+    b->left[slot] = 0;
+    b->admitted[slot] = 0;
+    std::memset((void*)&b->h_tab[slot], 0, sizeof(md::Sys));
+    s->batch = nullptr;
+    s->batch_slot = -1;
+    r = b->upload();
+    if (r != MD_OK) return r;
+    return s->sync_check();
+}
+
+md_status md_batch_sync(md_batch* b) {
+    if (!b) return MD_ERR_INVALID_ARG;
+    return b->hip(hipStreamSynchronize(b->stream), "batch sync");
+}
+
+md_status md_batch_info(const md_batch* b, md_batch_info_t* out) {
+    if (!b || !out) return MD_ERR_INVALID_ARG;
+    out->active = b->active;
+    out->lds_cap = b->lds_cap;
+    out->particles = b->particles;
+    out->bytes = b->bytes;
+    out->launches = b->launches;
+    out->captures = b->captures;
+    return MD_OK;
+}
+
+void md_batch_destroy(md_batch* b) {
+    if (!b) return;
+    for (int k = 0; k < b->p.max_systems; k++)
+        if (b->slot[k]) (void)md_batch_retire(b, k);
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+const char* md_batch_last_error(const md_batch* b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"

@@ -110,9 +110,55 @@ struct Sys {
     double* kpart;   // per-particle kinetic energy
     double* red;     // reduction partials (3 * kRedBlocks) + result (3)
     Ctrl* ctrl;
+    int eblk;        // blocks of the edge pass (grid-stride over the half list)
+    int prec;        // md_precision of the pair maths
 };
 
 constexpr int kRedBlocks = 1024;
+
+// ---------------------------------------------------------------------------
+// Batched step.  A batch runs many independent systems through one fixed
+// kernel sequence per step.  Each kernel of the sequence belongs to a block
+// class that fixes how many blocks a system gets in it; a per-class map sends
+// every block of the (fixed, capacity-sized) grid to (slot, block of that
+// system), or to -1 for an idle block.  A block never serves two systems, so a
+// system's arithmetic does not depend on the others in the batch.
+// ---------------------------------------------------------------------------
+enum BatchClass {
+    kClsParticle = 0,  // ceil(n / kBlock)
+    kClsTile,          // ntiles (one block per tile of kTile slots)
+    kClsTileScan,      // ceil(ntiles / kBlock): one thread per tile
+    kClsCellSort,      // ceil(ncell * kWave / kBlock): one wavefront per cell
+    kClsSystem,        // 1 (single-workgroup scans)
+    kClsVertex,        // LJ: ntiles, patchy: ceil(n / kBlock)
+    kClsEdge,          // eblk
+    kNumClasses
+};
+
+struct BatchDev {
+    const Sys* tab;   // [max_systems] descriptors, indexed by slot
+    int* left;        // [max_systems] steps left; 0 for free slots
+    const int2* map[kNumClasses];  // [cap of the class]: (slot, block) or (-1, 0)
+    int nslots;
+};
+
+// Blocks a system takes in a class.
+__host__ __device__ inline int class_blocks(const Sys& s, int cls) {
+    switch (cls) {
+        case kClsParticle: return s.nblk;
+        case kClsTile: return s.ntiles;
+        case kClsTileScan: return (s.ntiles + kBlock - 1) / kBlock;
+        case kClsCellSort: return (int)(((long long)s.ncell * kWave + kBlock - 1) / kBlock);
+        case kClsSystem: return 1;
+        case kClsVertex: return s.pot == 0 ? s.ntiles : s.nblk;
+        default: return s.eblk;
+    }
+}
+
+// Enqueues `steps` batched steps (forces by `mode`) plus the step-count
+// update on `st`; every grid is sized by cap[class], dynamic LDS by lds_cap.
+hipError_t launch_batch_steps(const BatchDev& b, const int* cap, int lds_cap, int mode,
+                              int steps, hipStream_t st);
 
 // Host-side launchers (md_kernels.hip).  All enqueue on `st`.
 hipError_t launch_set_rebuild(const Sys& s, hipStream_t st);

@@ -262,9 +262,9 @@ __global__ void k_clear_ctrl(Ctrl* c) {
 // due, so the sequence can sit in every step without a host round trip.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) {
+__device__ __forceinline__ void b_cell_bin(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
-    int p = blockIdx.x * kBlock + threadIdx.x;
+    int p = bid * kBlock + threadIdx.x;
     if (p >= s.n) return;
     double4 x = s.pos[p];
     int cx = cell_coord(wrap_box(x.x, s.box), s.cell_inv, s.nc);
@@ -275,9 +275,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) {
     s.rank[p] = atomicAdd(&s.ccount[c], 1);
 }
 
+__global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) { b_cell_bin(s, blockIdx.x, gridDim.x); }
+
 // One workgroup: exclusive scan of the cell counts into cell_start, then the
 // counts are cleared for the next build.
-__global__ __launch_bounds__(kScanThreads) void k_cell_scan(Sys s) {
+__device__ __forceinline__ void b_cell_scan(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     __shared__ int sh[kScanThreads];
     int t = threadIdx.x;
@@ -308,22 +310,26 @@ __global__ __launch_bounds__(kScanThreads) void k_cell_scan(Sys s) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_scatter(Sys s) {
+__global__ __launch_bounds__(kScanThreads) void k_cell_scan(Sys s) { b_cell_scan(s, blockIdx.x, gridDim.x); }
+
+__device__ __forceinline__ void b_cell_scatter(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
-    int p = blockIdx.x * kBlock + threadIdx.x;
+    int p = bid * kBlock + threadIdx.x;
     if (p >= s.n) return;
     s.order[s.cstart[s.cell[p]] + s.rank[p]] = p;
 }
+
+__global__ __launch_bounds__(kBlock) void k_cell_scatter(Sys s) { b_cell_scatter(s, blockIdx.x, gridDim.x); }
 
 // One wavefront per cell puts the cell's members (scattered in atomic order)
 // in ascending order of their previous slot, so the slot order, and every sum
 // over a list, does not depend on atomic timing.  A member's rank is the
 // number of members with a smaller previous slot, counted with lane reads
 // over the cell (64 members at a time).  The ordered slots go to s.rank.
-__global__ __launch_bounds__(kBlock) void k_cell_sort(Sys s) {
+__device__ __forceinline__ void b_cell_sort(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int c = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+    const int c = (bid * kBlock + threadIdx.x) / kWave;
     if (c >= s.ncell) return;
     const int b = s.cstart[c], m = s.cstart[c + 1] - b;
     for (int k0 = 0; k0 < m; k0 += kWave) {
@@ -338,9 +344,11 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(Sys s) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reorder(Sys s) {
+__global__ __launch_bounds__(kBlock) void k_cell_sort(Sys s) { b_cell_sort(s, blockIdx.x, gridDim.x); }
+
+__device__ __forceinline__ void b_reorder(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
-    int k = blockIdx.x * kBlock + threadIdx.x;
+    int k = bid * kBlock + threadIdx.x;
     if (k >= s.n) return;
     int p = s.rank[k];  // previous slot of the particle that takes slot k
     double4 x = s.pos[p];
@@ -352,6 +360,8 @@ __global__ __launch_bounds__(kBlock) void k_reorder(Sys s) {
         s.tangm[k] = s.angm[p];
     }
 }
+
+__global__ __launch_bounds__(kBlock) void k_reorder(Sys s) { b_reorder(s, blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------------------
 // Tile regions (one thread per tile of kTile consecutive slots).  The tile's
@@ -373,9 +383,9 @@ __device__ __forceinline__ int cell_of_slot(const int* cstart, int ncell, int sl
     return lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_tiles(Sys s) {
+__device__ __forceinline__ void b_tiles(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
-    int t = blockIdx.x * kBlock + threadIdx.x;
+    int t = bid * kBlock + threadIdx.x;
     if (t >= s.ntiles) return;
     const int nc = s.nc;
     if (nc < 3 || s.pot != 0) {  // the patchy pass gathers from global memory
@@ -449,6 +459,8 @@ __global__ __launch_bounds__(kBlock) void k_tiles(Sys s) {
     s.tile_nseg[t] = nseg;
     atomicAdd(&s.ctrl->staged, 1);
 }
+
+__global__ __launch_bounds__(kBlock) void k_tiles(Sys s) { b_tiles(s, blockIdx.x, gridDim.x); }
 
 // Position of slot range [cb, ...) seen through image `code` inside a tile's
 // LDS image: base + (cb - begin) of the segment that holds it, or -1.
@@ -541,12 +553,12 @@ __device__ __forceinline__ void region_finish(const Sys& s, const double4* src, 
 // lengths (entries with j > i) feed the half-list offsets.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kBlock) void k_build(Sys s, int unused) {
+__device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     extern __shared__ double lds[];
     __shared__ int red[kBlock / kWave];
     constexpr int TPP = kTileTpp;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = bid;
     const int i = tile * kTile + threadIdx.x / TPP;
     const int q = threadIdx.x % TPP;
     const int lane = threadIdx.x & (kWave - 1);
@@ -669,8 +681,10 @@ __global__ __launch_bounds__(kBlock) void k_build(Sys s, int unused) {
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_build(Sys s) { b_build(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+
 // One workgroup: exclusive scan of the per-tile half totals.
-__global__ __launch_bounds__(kScanThreads) void k_half_scan(Sys s) {
+__device__ __forceinline__ void b_half_scan(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     __shared__ long long sh[kScanThreads];
     int t = threadIdx.x;
@@ -701,18 +715,20 @@ __global__ __launch_bounds__(kScanThreads) void k_half_scan(Sys s) {
     }
 }
 
+__global__ __launch_bounds__(kScanThreads) void k_half_scan(Sys s) { b_half_scan(s, blockIdx.x, gridDim.x); }
+
 // Half list (edge pass): one workgroup per tile, four lanes per particle.
 // Row starts are the tile offset plus a prefix over the tile's particles; a
 // staged tile first maps its LDS indices back to slots (in LDS); each
 // particle's lanes walk its full list and keep the entries with j > i,
 // compacted with a ballot (list order is kept).  Records the chunk heads
 // (first row of every 64-entry chunk) that the edge pass uses.
-__global__ __launch_bounds__(kBlock) void k_half_fill(Sys s) {
+__device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     extern __shared__ int map[];
     __shared__ int hpre[kTile];
     constexpr int TPP = kTileTpp;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = bid;
     const int i = tile * kTile + threadIdx.x / TPP;
     const int q = threadIdx.x % TPP;
     const int lane = threadIdx.x & (kWave - 1);
@@ -771,6 +787,8 @@ __global__ __launch_bounds__(kBlock) void k_half_fill(Sys s) {
         k += __builtin_popcount(grp);
     }
 }
+
+__global__ __launch_bounds__(kBlock) void k_half_fill(Sys s) { b_half_fill(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
 
 // ---------------------------------------------------------------------------
 // Vertex decomposition: one thread per particle, no atomics.  Each thread
@@ -938,14 +956,14 @@ __device__ __forceinline__ void lj_lds_term(const Sys& s, const double* lds, int
 // under a wave-uniform trip count (entries past the list end point at the
 // padding slot).  Unstaged tiles gather from global memory.
 template <int PREC, int TPP, bool KICK, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) {
+__device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     static_assert(TPP * kTile == kBlock, "one tile per workgroup");
     static_assert(kPrefetch % 4 == 0, "groups of four");
     extern __shared__ double lds[];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = bid;
     const int i = tile * kTile + threadIdx.x / TPP;
     const int q = threadIdx.x % TPP;
-    if (KICK && blockIdx.x == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
+    if (KICK && bid == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
     const int nseg = s.tile_nseg[tile];
     const int cap = s.lds_cap;
     bool act = i < s.n;
@@ -1034,12 +1052,15 @@ __global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) {
     }
 }
 
+template <int PREC, int TPP, bool KICK, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) { b_vertex_lj<PREC, TPP, KICK, ENERGY>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+
 template <int PREC, bool KICK, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) {
+__device__ __forceinline__ void b_vertex_patchy(const Sys& s, int bid, int nb) {
     using R = typename std::conditional<PREC == 0, double, float>::type;
-    int lb = xcd_remap(blockIdx.x, gridDim.x);
+    int lb = bid;
     int i = lb * kBlock + threadIdx.x;
-    if (KICK && blockIdx.x == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
+    if (KICK && bid == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
     if (i >= s.n) return;
     double4 xi = s.pos[i];
     V3<double> ui[4];
@@ -1047,9 +1068,9 @@ __global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) {
     int cnt = s.ncount[i];
     Acc3<PREC> f, t;
     double e = 0, w = 0;
-    const int* nb = list_row(s, i);
+    const int* row = list_row(s, i);
     for (int k = 0; k < cnt; k++) {
-        int ent = nb[list_off(k)];
+        int ent = row[list_off(k)];
         int j = entry_slot(ent);
         double4 xj = s.pos[j];
         double dx = xj.x - xi.x + image(ent, 0, s.box);
@@ -1095,6 +1116,9 @@ __global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) {
     }
 }
 
+template <int PREC, bool KICK, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) { b_vertex_patchy<PREC, KICK, ENERGY>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+
 // ---------------------------------------------------------------------------
 // Edge decomposition: one lane per half-list entry (pair i < j).  The lane
 // evaluates the pair once; if the result is exactly zero it writes nothing,
@@ -1125,13 +1149,13 @@ __device__ __forceinline__ double seg_sum(double v, int key, int lane) {
 }
 
 template <int POT, int PREC>
-__global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
+__device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
     using R = typename std::conditional<PREC == 0, double, float>::type;
     const long long npairs = s.ctrl->npairs;
     const long long nchunks = (npairs + kWave - 1) / kWave;
     const int lane = threadIdx.x & (kWave - 1);
-    const long long nw = (long long)gridDim.x * (kBlock / kWave);
-    const long long w0 = (long long)xcd_remap(blockIdx.x, gridDim.x) * (kBlock / kWave) +
+    const long long nw = (long long)nb * (kBlock / kWave);
+    const long long w0 = (long long)bid * (kBlock / kWave) +
                          threadIdx.x / kWave;
     double* F = reinterpret_cast<double*>(s.frc);
     double* T = reinterpret_cast<double*>(s.trq);
@@ -1235,6 +1259,9 @@ __global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
     }
 }
 
+template <int POT, int PREC>
+__global__ __launch_bounds__(kBlock) void k_edge(Sys s) { b_edge<POT, PREC>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+
 // ---------------------------------------------------------------------------
 // Velocity Verlet (FP64).  kick_drift: v += dt/2 F/m, x += dt v, wrap into
 // [0, L); patchy also L += dt/2 tau and a free rotation of q by |L|/I dt
@@ -1243,8 +1270,8 @@ __global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
 // ---------------------------------------------------------------------------
 
 template <int POT, bool ZERO>
-__global__ __launch_bounds__(kBlock) void k_kick_drift(Sys s) {
-    int i = blockIdx.x * kBlock + threadIdx.x;
+__device__ __forceinline__ void b_kick_drift(const Sys& s, int bid, int nb) {
+    int i = bid * kBlock + threadIdx.x;
     if (i >= s.n) return;
     double4 f = s.frc[i];
     double4 v = s.vel[i];
@@ -1288,10 +1315,13 @@ __global__ __launch_bounds__(kBlock) void k_kick_drift(Sys s) {
     if (ddx * ddx + ddy * ddy + ddz * ddz > s.disp2) s.ctrl->rebuild = 1;
 }
 
+template <int POT, bool ZERO>
+__global__ __launch_bounds__(kBlock) void k_kick_drift(Sys s) { b_kick_drift<POT, ZERO>(s, blockIdx.x, gridDim.x); }
+
 template <int POT>
-__global__ __launch_bounds__(kBlock) void k_kick(Sys s) {
-    int i = blockIdx.x * kBlock + threadIdx.x;
-    if (blockIdx.x == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
+__device__ __forceinline__ void b_kick(const Sys& s, int bid, int nb) {
+    int i = bid * kBlock + threadIdx.x;
+    if (bid == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
     if (i >= s.n) return;
     double4 f = s.frc[i];
     double4 v = s.vel[i];
@@ -1311,6 +1341,9 @@ __global__ __launch_bounds__(kBlock) void k_kick(Sys s) {
     }
     if (!isfinite(chk)) atomicOr(&s.ctrl->nonfinite, 1);
 }
+
+template <int POT>
+__global__ __launch_bounds__(kBlock) void k_kick(Sys s) { b_kick<POT>(s, blockIdx.x, gridDim.x); }
 
 __global__ __launch_bounds__(kBlock) void k_zero_forces(Sys s) {
     int i = blockIdx.x * kBlock + threadIdx.x;
@@ -1405,7 +1438,7 @@ hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) 
         hipLaunchKernelGGL(k_tiles, grid_n(s.ntiles), dim3(kBlock), 0, st, s);
         size_t sh_pos = 3 * sizeof(double) * (size_t)(s.lds_cap + 8);
         size_t sh_map = sizeof(int) * (size_t)(s.lds_cap + 8);
-        hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), sh_pos, st, s, 0);
+        hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), sh_pos, st, s);
         hipLaunchKernelGGL(k_half_scan, dim3(1), dim3(kScanThreads), 0, st, s);
         hipLaunchKernelGGL(k_half_fill, dim3(s.ntiles), dim3(kBlock), sh_map, st, s);
     }
@@ -1511,6 +1544,141 @@ hipError_t launch_energy(const Sys& s, int prec, hipStream_t st) {
     else hipLaunchKernelGGL(k_kinetic<1>, grid_n(s.n), dim3(kBlock), 0, st, s);
     hipLaunchKernelGGL(k_reduce_partial, dim3(kRedBlocks), dim3(kBlock), 0, st, s);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedBlocks), 0, st, s);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched step.  The kernels below run the same bodies as the single-system
+// kernels, one system per block: block b of a kernel of class C serves
+// (slot, block) = map[C][b].  Idle blocks and slots whose steps for this
+// launch are used up return at once.  The descriptor is copied into registers
+// once per block, so later stores cannot force it to be reloaded.
+// ---------------------------------------------------------------------------
+
+template <int CLS, typename F>
+__device__ __forceinline__ void batch_block(const BatchDev& b, int step, F&& body) {
+    const int2 m = b.map[CLS][blockIdx.x];
+    if (m.x < 0 || step >= b.left[m.x]) return;
+    const Sys s = b.tab[m.x];
+    body(s, m.y);
+}
+
+template <bool ZERO>
+__global__ __launch_bounds__(kBlock) void kb_kick_drift(BatchDev b, int step) {
+    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) {
+        if (s.pot == 0) b_kick_drift<0, ZERO>(s, lb, s.nblk);
+        else b_kick_drift<1, ZERO>(s, lb, s.nblk);
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_cell_bin(BatchDev b, int step) {
+    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_cell_bin(s, lb, s.nblk); });
+}
+
+__global__ __launch_bounds__(kScanThreads) void kb_cell_scan(BatchDev b, int step) {
+    batch_block<kClsSystem>(b, step, [](const Sys& s, int lb) { b_cell_scan(s, lb, 1); });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_cell_scatter(BatchDev b, int step) {
+    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_cell_scatter(s, lb, s.nblk); });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_cell_sort(BatchDev b, int step) {
+    batch_block<kClsCellSort>(b, step, [](const Sys& s, int lb) {
+        b_cell_sort(s, lb, class_blocks(s, kClsCellSort));
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_reorder(BatchDev b, int step) {
+    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_reorder(s, lb, s.nblk); });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_tiles(BatchDev b, int step) {
+    batch_block<kClsTileScan>(b, step, [](const Sys& s, int lb) {
+        b_tiles(s, lb, class_blocks(s, kClsTileScan));
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_build(BatchDev b, int step) {
+    batch_block<kClsTile>(b, step, [](const Sys& s, int lb) { b_build(s, lb, s.ntiles); });
+}
+
+__global__ __launch_bounds__(kScanThreads) void kb_half_scan(BatchDev b, int step) {
+    batch_block<kClsSystem>(b, step, [](const Sys& s, int lb) { b_half_scan(s, lb, 1); });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_half_fill(BatchDev b, int step) {
+    batch_block<kClsTile>(b, step, [](const Sys& s, int lb) { b_half_fill(s, lb, s.ntiles); });
+}
+
+// Vertex forces with the closing half kick, dispatched per block on the
+// system's potential and precision (uniform branches).
+__global__ __launch_bounds__(kBlock) void kb_vertex(BatchDev b, int step) {
+    batch_block<kClsVertex>(b, step, [](const Sys& s, int lb) {
+        constexpr int T = kTileTpp;
+        if (s.pot == 0) {
+            if (s.prec == 0) b_vertex_lj<0, T, true, false>(s, lb, s.ntiles);
+            else if (s.prec == 1) b_vertex_lj<1, T, true, false>(s, lb, s.ntiles);
+            else b_vertex_lj<2, T, true, false>(s, lb, s.ntiles);
+        } else {
+            if (s.prec == 0) b_vertex_patchy<0, true, false>(s, lb, s.nblk);
+            else if (s.prec == 1) b_vertex_patchy<1, true, false>(s, lb, s.nblk);
+            else b_vertex_patchy<2, true, false>(s, lb, s.nblk);
+        }
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_edge(BatchDev b, int step) {
+    batch_block<kClsEdge>(b, step, [](const Sys& s, int lb) {
+        if (s.pot == 0) {
+            if (s.prec == 0) b_edge<0, 0>(s, lb, s.eblk);
+            else b_edge<0, 1>(s, lb, s.eblk);
+        } else {
+            if (s.prec == 0) b_edge<1, 0>(s, lb, s.eblk);
+            else b_edge<1, 1>(s, lb, s.eblk);
+        }
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_kick(BatchDev b, int step) {
+    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) {
+        if (s.pot == 0) b_kick<0>(s, lb, s.nblk);
+        else b_kick<1>(s, lb, s.nblk);
+    });
+}
+
+// Closes a launch of `steps` steps: every slot's budget drops by what it ran.
+__global__ __launch_bounds__(kBlock) void kb_advance(BatchDev b, int steps) {
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < b.nslots) b.left[i] = max(0, b.left[i] - steps);
+}
+
+hipError_t launch_batch_steps(const BatchDev& b, const int* cap, int lds_cap, int mode,
+                              int steps, hipStream_t st) {
+    const size_t sh_pos = 3 * sizeof(double) * (size_t)(lds_cap + 8);
+    const size_t sh_map = sizeof(int) * (size_t)(lds_cap + 8);
+    auto g = [&](int cls) { return dim3((unsigned)cap[cls]); };
+    const dim3 blk(kBlock), scan(kScanThreads);
+    for (int k = 0; k < steps; k++) {
+        if (mode == 0) hipLaunchKernelGGL(kb_kick_drift<false>, g(kClsParticle), blk, 0, st, b, k);
+        else hipLaunchKernelGGL(kb_kick_drift<true>, g(kClsParticle), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_cell_bin, g(kClsParticle), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_cell_scan, g(kClsSystem), scan, 0, st, b, k);
+        hipLaunchKernelGGL(kb_cell_scatter, g(kClsParticle), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_cell_sort, g(kClsCellSort), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_reorder, g(kClsParticle), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_tiles, g(kClsTileScan), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_build, g(kClsTile), blk, sh_pos, st, b, k);
+        hipLaunchKernelGGL(kb_half_scan, g(kClsSystem), scan, 0, st, b, k);
+        hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
+        if (mode == 0) {
+            hipLaunchKernelGGL(kb_vertex, g(kClsVertex), blk, sh_pos, st, b, k);
+        } else {
+            hipLaunchKernelGGL(kb_edge, g(kClsEdge), blk, 0, st, b, k);
+            hipLaunchKernelGGL(kb_kick, g(kClsParticle), blk, 0, st, b, k);
+        }
+    }
+    hipLaunchKernelGGL(kb_advance, dim3((b.nslots + kBlock - 1) / kBlock), blk, 0, st, b, steps);
     return hipGetLastError();
 }
 

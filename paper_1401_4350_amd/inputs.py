@@ -122,3 +122,40 @@ def make_state(w: Workload, seed: int, attempt: int = 0) -> State:
         q /= np.linalg.norm(q, axis=1, keepdims=True)
         am = rng.normal(0.0, math.sqrt(w.inertia * w.temp), size=(n, 3))
     return State(x=x, v=v, q=q, angmom=am, box=L, seed=seed, attempt=attempt)
+
+
+@dataclass(frozen=True)
+class Request:
+    """One serving request: simulate `workload` (its n, potential, density and
+    step count) from make_state(workload, seed)."""
+    rid: int
+    arrival: float  # seconds after the stream starts
+    workload: Workload
+    seed: int
+
+
+def serving_requests(count: int, rate_hz: float, seed: int = 0, steps: int = 1000,
+                     n_min: int = 500, n_max: int = 50000,
+                     patchy_share: float = 0.3) -> list[Request]:
+    """A stream of independent simulation requests.
+
+    Recipe (numpy PCG64 ``default_rng(seed)``, four draws per request in this
+    order): exponential inter-arrival gap of mean 1/rate_hz (Poisson
+    arrivals); log N uniform in [log n_min, log n_max], rounded; patchy with
+    probability patchy_share, else LJ; density U[0.3, 0.6] for patchy and
+    U[0.6, 0.9] for LJ.  The LJ and patchy requests otherwise take the
+    parameters of the lj_small and patchy workloads (cut-offs, temperature,
+    skin, dt).  Request k's state seed is 1 + k.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    for k in range(count):
+        t += rng.exponential(1.0 / rate_hz)
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        patchy = rng.random() < patchy_share
+        rho = rng.uniform(0.3, 0.6) if patchy else rng.uniform(0.6, 0.9)
+        base = WORKLOADS["patchy" if patchy else "lj_small"]
+        w = base.with_(name=f"req{k}", n=n, rho=float(rho), steps=steps)
+        out.append(Request(rid=k, arrival=t, workload=w, seed=1 + k))
+    return out

@@ -57,9 +57,24 @@ class MDProfile(ctypes.Structure):
                 ("rebuild_ms", ctypes.c_double), ("force_ms", ctypes.c_double)]
 
 
+class MDBatchParams(ctypes.Structure):
+    _fields_ = [("max_systems", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("max_particles", ctypes.c_int64), ("pool_bytes", ctypes.c_uint64)]
+
+
+class MDBatchInfo(ctypes.Structure):
+    _fields_ = [("active", ctypes.c_int32), ("lds_cap", ctypes.c_int32),
+                ("particles", ctypes.c_int64), ("bytes", ctypes.c_uint64),
+                ("launches", ctypes.c_int64), ("captures", ctypes.c_int64)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
 _sys_p = ctypes.c_void_p
+_bat_p = ctypes.c_void_p
+_I32P = ctypes.POINTER(ctypes.c_int32)
+_I64P = ctypes.POINTER(ctypes.c_int64)
 
 _SIGS = {
     "md_query_sizes": ([ctypes.POINTER(MDParams), ctypes.POINTER(MDSizes)], ctypes.c_int),
@@ -81,6 +96,18 @@ _SIGS = {
     "md_destroy": ([_sys_p], None),
     "md_status_str": ([ctypes.c_int32], ctypes.c_char_p),
     "md_last_error": ([_sys_p], ctypes.c_char_p),
+    "md_batch_query_sizes": ([ctypes.POINTER(MDBatchParams), ctypes.POINTER(ctypes.c_uint64)],
+                             ctypes.c_int),
+    "md_batch_create": ([ctypes.POINTER(MDBatchParams), _P, ctypes.c_uint64, _P,
+                         ctypes.POINTER(_bat_p)], ctypes.c_int),
+    "md_batch_admit": ([_bat_p, _sys_p, ctypes.c_int64, _I32P], ctypes.c_int),
+    "md_batch_step": ([_bat_p, _I32P], ctypes.c_int),
+    "md_batch_steps_left": ([_bat_p, ctypes.c_int32, _I64P], ctypes.c_int),
+    "md_batch_retire": ([_bat_p, ctypes.c_int32], ctypes.c_int),
+    "md_batch_sync": ([_bat_p], ctypes.c_int),
+    "md_batch_info": ([_bat_p, ctypes.POINTER(MDBatchInfo)], ctypes.c_int),
+    "md_batch_destroy": ([_bat_p], None),
+    "md_batch_last_error": ([_bat_p], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -234,6 +261,99 @@ class System:
         return dict(steps=s.steps, rebuilds=s.rebuilds, pairs=s.pairs,
                     max_list_len=s.max_list_len, n_cells=s.n_cells,
                     tiles_total=s.tiles_total, tiles_staged=s.tiles_staged)
+
+
+def batch_params(max_systems: int, max_particles: int, pool_bytes: int, mode: str = "vertex",
+                 steps_per_launch: int = 64, use_graph: bool = True) -> MDBatchParams:
+    p = MDBatchParams()
+    p.max_systems, p.mode, p.steps_per_launch = max_systems, MODE[mode], steps_per_launch
+    p.use_graph, p.max_particles, p.pool_bytes = int(use_graph), max_particles, pool_bytes
+    return p
+
+
+def batch_workspace_bytes(p: MDBatchParams) -> int:
+    b = ctypes.c_uint64()
+    st = _lib.md_batch_query_sizes(ctypes.byref(p), ctypes.byref(b))
+    if st != MD_OK:
+        raise MDError(st, "md_batch_query_sizes")
+    return int(b.value)
+
+
+class Batch:
+    """Batched serving handle (md_batch_* in include/md.h).  Holds a reference
+    to every admitted System so its buffers outlive the admission."""
+
+    def __init__(self, params: MDBatchParams, stream: torch.cuda.Stream | None = None):
+        self.params = params
+        nbytes = batch_workspace_bytes(params)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        a = 256
+        self._ws = torch.empty(nbytes + a, dtype=torch.uint8, device=dev)
+        wp = (self._ws.data_ptr() + a - 1) // a * a
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _bat_p()
+        st = _lib.md_batch_create(ctypes.byref(params), wp, nbytes, self.stream.cuda_stream,
+                                  ctypes.byref(h))
+        if st != MD_OK:
+            raise MDError(st, "md_batch_create")
+        self._h = h
+        self.systems: dict[int, System] = {}
+
+    def _check(self, st, what):
+        if st != MD_OK:
+            raise MDError(st, f"{what}: {_lib.md_batch_last_error(self._h).decode()}")
+
+    def admit(self, system: System, nsteps: int) -> int:
+        slot = ctypes.c_int32()
+        self._check(_lib.md_batch_admit(self._h, system._h, nsteps, ctypes.byref(slot)),
+                    "md_batch_admit")
+        self.systems[slot.value] = system
+        return slot.value
+
+    def try_admit(self, system: System, nsteps: int) -> int | None:
+        """Slot, or None when the batch has no room (MD_ERR_BUFFER_TOO_SMALL)."""
+        try:
+            return self.admit(system, nsteps)
+        except MDError as e:
+            if e.status == -2:
+                return None
+            raise
+
+    def step(self) -> int:
+        k = ctypes.c_int32()
+        self._check(_lib.md_batch_step(self._h, ctypes.byref(k)), "md_batch_step")
+        return k.value
+
+    def steps_left(self, slot: int) -> int:
+        v = ctypes.c_int64()
+        self._check(_lib.md_batch_steps_left(self._h, slot, ctypes.byref(v)), "md_batch_steps_left")
+        return v.value
+
+    def retire(self, slot: int) -> System:
+        system = self.systems.pop(slot)
+        self._check(_lib.md_batch_retire(self._h, slot), "md_batch_retire")
+        return system
+
+    def sync(self):
+        self._check(_lib.md_batch_sync(self._h), "md_batch_sync")
+
+    def info(self) -> dict:
+        i = MDBatchInfo()
+        self._check(_lib.md_batch_info(self._h, ctypes.byref(i)), "md_batch_info")
+        return dict(active=i.active, lds_cap=i.lds_cap, particles=i.particles, bytes=i.bytes,
+                    launches=i.launches, captures=i.captures)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.md_batch_destroy(self._h)
+            self._h = None
+            self.systems.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def lib():

@@ -92,3 +92,39 @@ def test_null_handle_calls(md):
     assert lib.md_step(None, 1, 0) == -1
     assert lib.md_status_str(-4).decode().startswith("Verlet list overflow")
     assert lib.md_last_error(None).decode() == ""
+
+
+def test_batch_params_checked_on_host(md):
+    lib = md.lib()
+    ok = md.batch_params(8, 100000, 1 << 30)
+    assert md.batch_workspace_bytes(ok) > 0
+    n = ctypes.c_uint64()
+    h = ctypes.c_void_p()
+    for field, value in [("max_systems", 0), ("mode", 3), ("steps_per_launch", 0),
+                         ("steps_per_launch", 5000), ("use_graph", 2), ("max_particles", 1),
+                         ("pool_bytes", 0)]:
+        p = md.batch_params(8, 100000, 1 << 30)
+        setattr(p, field, value)
+        assert lib.md_batch_query_sizes(ctypes.byref(p), ctypes.byref(n)) == -1, field
+        assert lib.md_batch_create(ctypes.byref(p), 256, 1 << 40, None, ctypes.byref(h)) == -1
+        assert not h.value
+    need = md.batch_workspace_bytes(ok)
+    assert lib.md_batch_create(ctypes.byref(ok), 256, need - 1, None, ctypes.byref(h)) == -2
+    assert lib.md_batch_create(ctypes.byref(ok), 257, need, None, ctypes.byref(h)) == -2
+    assert lib.md_batch_create(ctypes.byref(ok), None, need, None, ctypes.byref(h)) == -1
+    # the workspace grows with the block-class capacities
+    big = md.batch_params(8, 1000000, 1 << 30)
+    assert md.batch_workspace_bytes(big) > need
+
+
+def test_batch_null_handle_calls(md):
+    lib = md.lib()
+    k = ctypes.c_int32()
+    v = ctypes.c_int64()
+    assert lib.md_batch_admit(None, None, 1, ctypes.byref(k)) == -1
+    assert lib.md_batch_step(None, ctypes.byref(k)) == -1
+    assert lib.md_batch_steps_left(None, 0, ctypes.byref(v)) == -1
+    assert lib.md_batch_retire(None, 0) == -1
+    assert lib.md_batch_sync(None) == -1
+    assert lib.md_batch_last_error(None).decode() == ""
+    lib.md_batch_destroy(None)
