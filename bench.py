@@ -90,6 +90,35 @@ def cpu_baseline(w, state, pairs, budget_s=20.0):
             "steps_per_s": k / dt}
 
 
+def serving_bench(count, rate, steps, max_systems=64):
+    """Continuous batching of a Poisson stream of independent requests (N
+    log-uniform in [500, 50000], 70 % LJ / 30 % patchy; inputs.serving_requests)
+    through md_batch_*, against the single-system path serving the same stream
+    one request at a time.  Reports p50/p99 time-to-completion and aggregate
+    pair evaluations per second."""
+    from paper_1401_4350_amd.inputs import serving_requests
+    from paper_1401_4350_amd.serve import (GpuExecutor, Scheduler, SequentialExecutor,
+                                           footprint_bytes, summarize)
+    reqs = serving_requests(count, rate, seed=0, steps=steps)
+    pool = 64 << 30
+    out = {"requests": count, "rate_per_s": rate, "steps_per_request": steps,
+           "footprint_max_MB": max(footprint_bytes(r) for r in reqs) / 2 ** 20,
+           "footprint_mean_MB": sum(footprint_bytes(r) for r in reqs) / count / 2 ** 20}
+    for prec in ("fp32", "fp64"):
+        ex = GpuExecutor(max_systems, sum(r.workload.n for r in reqs), pool, "vertex", prec, 64)
+        rep = Scheduler(ex, pool, max_systems).run(reqs)
+        s = summarize(rep)
+        s["captures"] = ex.batch.info()["captures"]
+        ex.close()
+        out[f"batched_{prec}"] = s
+    for prec in ("fp64", "fp32"):
+        ex = SequentialExecutor("vertex", prec)
+        out[f"single_{prec}"] = summarize(Scheduler(ex, pool, 1).run(reqs))
+    b, a = out["batched_fp32"], out["single_fp64"]
+    out["throughput_gain_vs_single_fp64"] = b["pair_evals_per_s"] / a["pair_evals_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +130,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="time only the headline (vertex) and edge modes")
+    ap.add_argument("--serving-requests", type=int, default=48,
+                    help="requests of the serving comparison (0: skip it)")
+    ap.add_argument("--serving-rate", type=float, default=400.0)
+    ap.add_argument("--serving-steps", type=int, default=1000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -182,6 +215,9 @@ def main():
                      "bytes_per_launch": nb, "avg_launch_us": t_kernel * 1e6},
         "modes": modes,
     }
+    if args.serving_requests > 0:
+        out["serving"] = serving_bench(args.serving_requests, args.serving_rate,
+                                       args.serving_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, state, pairs)
     print(json.dumps(out), flush=True)

@@ -71,7 +71,8 @@ def lib():
         L.or_lj_pair.argtypes = [ctypes.c_double] * 4 + [_D]
         L.or_lj_forces.restype = None
         L.or_lj_forces.argtypes = [ctypes.c_int, _D, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]
+                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, _D, _D, _D, _D,
+                                   _D]
         L.or_lj_force_one.restype = None
         L.or_lj_force_one.argtypes = [ctypes.c_int, ctypes.c_int, _D, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double, _D, _D]
@@ -164,17 +165,24 @@ def lj_pair(r2, p: LJ):
     return v, fs.value
 
 
-def lj_forces(x, L, p: LJ, use_cells=True, with_abs=False):
-    """(F (N,3), e (N,), w (N,)[, Fabs (N,3)]) summed over all j with r < rcut."""
+def lj_forces(x, L, p: LJ, use_cells=True, with_abs=False, with_eabs=False):
+    """(F (N,3), e (N,), w (N,)[, Fabs (N,3)][, Eabs (N,)]) summed over all j
+    with r < rcut; Fabs and Eabs are the term-magnitude scales of F and e."""
     x = _f64(x, (-1, 3))
     n = x.shape[0]
     F = np.zeros((n, 3))
     e = np.zeros(n)
     w = np.zeros(n)
     A = np.zeros((n, 3))
+    EA = np.zeros(n)
     lib().or_lj_forces(n, _d(x), L, p.eps, p.sigma, p.rcut, int(use_cells), _d(F), _d(e),
-                       _d(w), _d(A))
-    return (F, e, w, A) if with_abs else (F, e, w)
+                       _d(w), _d(A), _d(EA))
+    out = (F, e, w)
+    if with_abs:
+        out += (A,)
+    if with_eabs:
+        out += (EA,)
+    return out
 
 
 def lj_force_one(i, x, L, p: LJ):

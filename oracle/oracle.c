@@ -189,9 +189,18 @@ double or_lj_pair(double r2, double eps, double sigma, double rc, double* fscal)
     return lj_v(r2, eps, sigma) - lj_v(rc * rc, eps, sigma);
 }
 
+/* Magnitude scale of one pair energy: the sum of the absolute values of its
+ * three additive terms, 4 eps (sigma/r)^12, 4 eps (sigma/r)^6 and the shift
+ * V(rc).  Rounding errors of any evaluation of V are measured against it. */
+static double lj_v_scale(double r2, double eps, double sigma, double rc) {
+    double s2 = sigma * sigma / r2;
+    double s6 = s2 * s2 * s2;
+    return fabs(4.0 * eps * s6 * s6) + fabs(4.0 * eps * s6) + fabs(lj_v(rc * rc, eps, sigma));
+}
+
 static void lj_accumulate(const double* x, int i, int j, double L, double eps,
                           double sigma, double rc2, double rc, double* f3, double* e,
-                          double* w, double* a3) {
+                          double* w, double* a3, double* ea) {
     double d[3];
     double r2 = sep(x, i, j, L, d);
     if (r2 < rc2) {
@@ -203,33 +212,35 @@ static void lj_accumulate(const double* x, int i, int j, double L, double eps,
             a3[c] += fabs(fs * d[c]);
         }
         *e += 0.5 * v;
+        *ea += 0.5 * lj_v_scale(r2, eps, sigma, rc);
         *w += 0.5 * fs * r2; /* r_ij . F_j */
     }
 }
 
 void or_lj_force_one(int i, int n, const double* x, double L, double eps, double sigma,
                      double rc, double* f3, double* e) {
-    double rc2 = rc * rc, w = 0, a3[3] = {0, 0, 0};
+    double rc2 = rc * rc, w = 0, a3[3] = {0, 0, 0}, ea = 0;
     f3[0] = f3[1] = f3[2] = 0;
     *e = 0;
     for (int j = 0; j < n; j++)
-        if (j != i) lj_accumulate(x, i, j, L, eps, sigma, rc2, rc, f3, e, &w, a3);
+        if (j != i) lj_accumulate(x, i, j, L, eps, sigma, rc2, rc, f3, e, &w, a3, &ea);
 }
 
 void or_lj_forces(int n, const double* x, double L, double eps, double sigma, double rc,
-                  int use_cells, double* F, double* e, double* w, double* Fabs) {
+                  int use_cells, double* F, double* e, double* w, double* Fabs, double* Eabs) {
     double rc2 = rc * rc;
     cells_t cl;
     int have = use_cells ? cells_build(&cl, n, x, L, rc) : 0;
     for (int i = 0; i < n; i++) {
-        double f3[3] = {0, 0, 0}, a3[3] = {0, 0, 0}, ei = 0, wi = 0;
+        double f3[3] = {0, 0, 0}, a3[3] = {0, 0, 0}, ei = 0, wi = 0, ea = 0;
         if (have) {
             FOR_CANDIDATES(cl, x, L, i, j, {
-                if (j != i) lj_accumulate(x, i, j, L, eps, sigma, rc2, rc, f3, &ei, &wi, a3);
+                if (j != i)
+                    lj_accumulate(x, i, j, L, eps, sigma, rc2, rc, f3, &ei, &wi, a3, &ea);
             });
         } else {
             for (int j = 0; j < n; j++)
-                if (j != i) lj_accumulate(x, i, j, L, eps, sigma, rc2, rc, f3, &ei, &wi, a3);
+                if (j != i) lj_accumulate(x, i, j, L, eps, sigma, rc2, rc, f3, &ei, &wi, a3, &ea);
         }
         for (int c = 0; c < 3; c++) {
             F[3 * i + c] = f3[c];
@@ -237,6 +248,7 @@ void or_lj_forces(int n, const double* x, double L, double eps, double sigma, do
         }
         if (e) e[i] = ei;
         if (w) w[i] = wi;
+        if (Eabs) Eabs[i] = ea;
     }
     if (have) cells_free(&cl);
 }
@@ -446,7 +458,7 @@ static void compute_forces(int n, const double* x, const double* q, double L,
                            const or_run_params* p, double* F, double* T, double* e,
                            double* w) {
     if (p->pot == 0)
-        or_lj_forces(n, x, L, p->eps, p->sigma, p->rcut, 1, F, e, w, NULL);
+        or_lj_forces(n, x, L, p->eps, p->sigma, p->rcut, 1, F, e, w, NULL, NULL);
     else
         or_patchy_forces(n, x, q, L, &p->patchy, 1, F, T, e, w, NULL, NULL);
 }

@@ -69,11 +69,12 @@ double or_lj_pair(double r2, double eps, double sigma, double rc, double* fscal)
  * per-particle virials w_i = 1/2 sum_j r_ij . F_j(ij), summing over every
  * j != i with r_ij < rc (each pair visited from both ends).  use_cells != 0
  * enumerates candidates with the oracle's own cell list.  Fabs (3N) gets
- * sum_j |F_ij,c|, the scale against which a differently ordered sum is judged.
- * e, w and Fabs may be NULL. */
+ * sum_j |F_ij,c|, the scale against which a differently ordered sum is judged;
+ * Eabs (N) gets 1/2 sum_j (|4 eps (sigma/r)^12| + |4 eps (sigma/r)^6| + |V(rc)|),
+ * the same kind of scale for e_i.  e, w, Fabs and Eabs may be NULL. */
 void or_lj_forces(int n, const double* x, double L, double eps, double sigma,
                   double rc, int use_cells, double* F, double* e, double* w,
-                  double* Fabs);
+                  double* Fabs, double* Eabs);
 
 /* Force and energy of one particle by brute force over all j. */
 void or_lj_force_one(int i, int n, const double* x, double L, double eps,

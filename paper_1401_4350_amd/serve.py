@@ -306,6 +306,53 @@ class GpuExecutor:
         self.batch.close()
 
 
+class SequentialExecutor:
+    """The single-system path as a server: one system at a time, all its
+    steps in one md_step call (for comparison with the batch; run it with a
+    Scheduler of max_slots=1)."""
+
+    def __init__(self, mode: str = "vertex", prec: str = "fp64"):
+        from . import md
+        self.md = md
+        self.mode, self.prec = mode, prec
+        self.sys = {}
+        self.next = 0
+        self.t0 = time.perf_counter()
+
+    now = GpuExecutor.now
+    wait_until = GpuExecutor.wait_until
+
+    def footprint(self, req: Request) -> int:
+        return footprint_bytes(req, self.prec)
+
+    def admit(self, req: Request):
+        md = self.md
+        st = make_state(req.workload, req.seed)
+        g = md.System(md.make_params(req.workload, self.prec))
+        g.set_state(st.x, st.v, st.q, st.angmom)
+        g.build()
+        g.forces(self.mode)
+        h = self.next
+        self.next += 1
+        self.sys[h] = [g, req.workload.steps]
+        return h
+
+    def step(self):
+        for item in self.sys.values():
+            if item[1] > 0:
+                item[0].step(item[1], self.mode)  # syncs
+                item[1] = 0
+
+    def finished(self):
+        return [h for h, item in self.sys.items() if item[1] == 0]
+
+    def retire(self, h, cancelled: bool = False) -> dict:
+        g, _ = self.sys.pop(h)
+        out = {"pairs": int(g.stats()["pairs"])}
+        g.close()
+        return out
+
+
 def footprint_bytes(req: Request, prec: str = "fp32") -> int:
     """HBM footprint of one request (state + workspace, md_query_sizes)."""
     from . import md

@@ -162,6 +162,24 @@ def test_virial_pair():
     assert wv.sum() == pytest.approx(fs * r * r, rel=1e-13)
 
 
+def test_energy_scale_pair_and_bound():
+    """The per-particle energy scale: for two particles at distance r it sums,
+    over both ends, to |4 (1/r)^12| + |4 (1/r)^6| + |V(rc)| (eps = sigma = 1),
+    and on a fluid it bounds |e_i| (triangle inequality over the terms)."""
+    L = 20.0
+    r = 1.3
+    x = np.array([[5.0, 5.0, 5.0], [5.0 + r, 5.0, 5.0]])
+    _, e, _, ea = oracle.lj_forces(x, L, oracle.LJ(), use_cells=False, with_eabs=True)
+    vrc = 4.0 * (2.5 ** -12 - 2.5 ** -6)
+    want = 4.0 * r ** -12 + 4.0 * r ** -6 + abs(vrc)
+    assert ea.sum() == pytest.approx(want, rel=1e-14)
+    assert ea[0] == pytest.approx(ea[1], rel=1e-15)
+    w, s = _small_fluid(n=500, seed=21)
+    _, e, _, ea = oracle.lj_forces(s.x, s.box, oracle.LJ(), with_eabs=True)
+    assert (ea >= np.abs(e) - 1e-15).all()
+    assert (ea > 0).all()
+
+
 def _run(s, w, nsteps, dt):
     return oracle.run(s.x, s.v, s.box, pot="lj", nsteps=nsteps, dt=dt, skin=w.skin,
                       lj=oracle.LJ(w.eps, w.sigma, w.rcut))
