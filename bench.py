@@ -104,19 +104,88 @@ def serving_bench(count, rate, steps, max_systems=64):
     out = {"requests": count, "rate_per_s": rate, "steps_per_request": steps,
            "footprint_max_MB": max(footprint_bytes(r) for r in reqs) / 2 ** 20,
            "footprint_mean_MB": sum(footprint_bytes(r) for r in reqs) / count / 2 ** 20}
-    for prec in ("fp32", "fp64"):
-        ex = GpuExecutor(max_systems, sum(r.workload.n for r in reqs), pool, "vertex", prec, 64)
+    for prec, graph in (("fp32", True), ("fp64", True), ("fp32", False)):
+        ex = GpuExecutor(max_systems, sum(r.workload.n for r in reqs), pool, "vertex", prec, 64,
+                         use_graph=graph)
         rep = Scheduler(ex, pool, max_systems).run(reqs)
         s = summarize(rep)
         s["captures"] = ex.batch.info()["captures"]
         ex.close()
-        out[f"batched_{prec}"] = s
+        out[f"batched_{prec}" + ("" if graph else "_direct_launches")] = s
     for prec in ("fp64", "fp32"):
         ex = SequentialExecutor("vertex", prec)
         out[f"single_{prec}"] = summarize(Scheduler(ex, pool, 1).run(reqs))
     b, a = out["batched_fp32"], out["single_fp64"]
     out["throughput_gain_vs_single_fp64"] = b["pair_evals_per_s"] / a["pair_evals_per_s"]
     return out
+
+
+def crossover_bench(torch, steps=100, warmup=20):
+    """Vertex against edge over system size and density, for both potentials:
+    per point the MD step and the force pass of each decomposition (FP64).
+    Sizes N = 2^10 .. 2^20 at each potential's own density (LJ 0.8, patchy
+    0.5), and densities 0.1, 0.3, 0.5, 0.8 at N = 2^17."""
+    from paper_1401_4350_amd import md
+    from paper_1401_4350_amd.inputs import WORKLOADS, make_state
+    points = []
+    for pot, base in (("lj", "lj_many"), ("patchy", "patchy")):
+        b = WORKLOADS[base]
+        grid = [(2 ** e, b.rho) for e in range(10, 21, 2)]
+        grid += [(2 ** 17, r) for r in (0.1, 0.3, 0.5, 0.8)]
+        for n, rho in grid:
+            w = b.with_(n=n, rho=rho)
+            if w.box <= 2 * w.rv:
+                continue
+            st = make_state(w, 1)
+            row = {"pot": pot, "n": n, "rho": rho}
+            for mode in ("vertex", "edge"):
+                r = time_mode(md, torch, w, st, mode, "fp64", steps, warmup)
+                row[f"{mode}_step_us"] = 1e3 * r["ms_per_step"]
+                row[f"{mode}_force_us"] = 1e3 * r["force_ms_per_step"]
+                row["pairs"] = r["pairs"]
+            row["edge_over_vertex_force"] = row["vertex_force_us"] / row["edge_force_us"]
+            row["faster"] = "edge" if row["edge_step_us"] < row["vertex_step_us"] else "vertex"
+            points.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    return points
+
+
+def drift_bench(torch, steps=10000, every=500):
+    """Total-energy drift of the 1M-particle LJ workload (dt = 0.005) over
+    `steps` velocity-Verlet steps for each precision variant: slope of a
+    least-squares line through E(t) sampled every `every` steps, per particle
+    and per 10 000 steps, plus the rms fluctuation about that line."""
+    import numpy as np
+    from paper_1401_4350_amd import md
+    from paper_1401_4350_amd.inputs import WORKLOADS, make_state
+    w = WORKLOADS["lj_precision"]
+    st = make_state(w, 1)
+    out = {}
+    for prec in ("fp64", "fp32", "fp32_kahan"):
+        g = md.System(md.make_params(w, prec))
+        g.set_state(st.x, st.v)
+        g.build()
+        g.forces("vertex")
+        ts, es = [], []
+        t_gpu = 0.0
+        for k in range(0, steps + 1, every):
+            if k:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.step(every, "vertex")
+                t_gpu += time.perf_counter() - t0
+            ke, pe, _ = g.energy()
+            ts.append(k)
+            es.append((ke + pe) / w.n)
+        g.close()
+        ts, es = np.array(ts, float), np.array(es)
+        slope, icpt = np.polyfit(ts, es, 1)
+        resid = es - (slope * ts + icpt)
+        out[prec] = {"drift_per_particle_per_10k_steps": slope * 1e4,
+                     "rms_fluctuation_per_particle": float(np.sqrt((resid ** 2).mean())),
+                     "e0_per_particle": float(es[0]), "ms_per_step": 1e3 * t_gpu / steps}
+        print(json.dumps({prec: out[prec]}), file=sys.stderr, flush=True)
+    return {"workload": w.name, "n": w.n, "dt": w.dt, "steps": steps, "variants": out}
 
 
 def main():
@@ -134,6 +203,10 @@ def main():
                     help="requests of the serving comparison (0: skip it)")
     ap.add_argument("--serving-rate", type=float, default=400.0)
     ap.add_argument("--serving-steps", type=int, default=1000)
+    ap.add_argument("--crossover", action="store_true",
+                    help="print the vertex/edge crossover sweep instead of the headline line")
+    ap.add_argument("--drift", action="store_true",
+                    help="print the energy-drift study of the precision variants instead")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -149,6 +222,12 @@ def main():
     from paper_1401_4350_amd.inputs import WORKLOADS, make_state
 
     torch.cuda.set_device(0)
+    if args.crossover:
+        print(json.dumps({"crossover": crossover_bench(torch)}), flush=True)
+        return
+    if args.drift:
+        print(json.dumps({"drift": drift_bench(torch)}), flush=True)
+        return
     w = WORKLOADS[args.workload]
     state = make_state(w, args.seed)
 

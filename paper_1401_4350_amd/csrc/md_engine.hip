@@ -661,7 +661,7 @@ BatchLayout batch_layout(const md_batch_params& p) {
     c[md::kClsParticle] = (nmax + md::kBlock - 1) / md::kBlock + smax;
     c[md::kClsTile] = tiles;
     c[md::kClsTileScan] = (tiles + md::kBlock - 1) / md::kBlock + smax;
-    c[md::kClsCellSort] = nmax * 2 / (md::kBlock / md::kWave) + smax;  // up to 2 cells per particle
+    c[md::kClsCellSort] = c[md::kClsParticle];  // at most nblk blocks per system
     c[md::kClsSystem] = smax;
     c[md::kClsVertex] = tiles;
     c[md::kClsEdge] = 4 * tiles;
@@ -706,7 +706,17 @@ struct md_batch {
     long long particles = 0;
     uint64_t bytes = 0;
     int lds_cap = 512;  // LDS region capacity the graphs are captured for
-    std::vector<std::pair<int, hipGraphExec_t>> graphs;  // by steps per launch
+    // Captured launches, keyed by steps and the grid of every class.  Grids
+    // are the blocks in use rounded up to a power of two, so admissions and
+    // retirements reuse a captured graph until a class crosses a power of two.
+    struct Graph {
+        int steps;
+        int grid[md::kNumClasses];
+        hipGraphExec_t exec;
+        long long used_at;
+    };
+    std::vector<Graph> graphs;
+    static constexpr size_t kMaxGraphs = 24;
     long long launches = 0, captures = 0;
     std::string err;
 
@@ -720,8 +730,21 @@ struct md_batch {
         return MD_ERR_HIP;
     }
     void drop_graphs() {
-        for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
         graphs.clear();
+    }
+    // Grid of every class for the current admissions: the blocks in use,
+    // rounded up to a power of two for captured graphs.
+    void grids(bool bucket, int* out) const {
+        for (int c = 0; c < md::kNumClasses; c++) {
+            int u = std::max(used[c], 1);
+            if (bucket) {
+                int g = 1;
+                while (g < u) g *= 2;
+                u = g;
+            }
+            out[c] = std::min(u, lay.cap[c]);
+        }
     }
     ~md_batch() {
         drop_graphs();
@@ -764,23 +787,38 @@ struct md_batch {
         return r;
     }
 
-    md_status graph_for(int steps, hipGraphExec_t* out) {
+    md_status graph_for(int steps, const int* grid, hipGraphExec_t* out) {
         for (auto& g : graphs)
-            if (g.first == steps) {
-                *out = g.second;
+            if (g.steps == steps && std::equal(grid, grid + md::kNumClasses, g.grid)) {
+                g.used_at = launches;
+                *out = g.exec;
                 return MD_OK;
             }
+        if (graphs.size() >= kMaxGraphs) {  // drop the least recently launched
+            auto old = std::min_element(graphs.begin(), graphs.end(), [](const Graph& a, const Graph& b) {
+                return a.used_at < b.used_at;
+            });
+            md_status r = hip(hipStreamSynchronize(stream), "graph eviction sync");
+            if (r != MD_OK) return r;
+            (void)hipGraphExecDestroy(old->exec);
+            graphs.erase(old);
+        }
         hipGraph_t graph = nullptr;
         md_status r = hip(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal), "begin capture");
         if (r != MD_OK) return r;
-        hipError_t e = md::launch_batch_steps(dev, lay.cap, lds_cap, p.mode, steps, capture);
+        hipError_t e = md::launch_batch_steps(dev, grid, lds_cap, p.mode, steps, capture);
         hipError_t e2 = hipStreamEndCapture(capture, &graph);
         r = hip(e != hipSuccess ? e : e2, "capture batch step");
         hipGraphExec_t exec = nullptr;
         if (r == MD_OK) r = hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
         if (graph) (void)hipGraphDestroy(graph);
         if (r != MD_OK) return r;
-        graphs.emplace_back(steps, exec);
+        Graph g;
+        g.steps = steps;
+        std::copy(grid, grid + md::kNumClasses, g.grid);
+        g.exec = exec;
+        g.used_at = launches;
+        graphs.push_back(g);
         captures++;
         *out = exec;
         return MD_OK;
@@ -893,12 +931,14 @@ md_status md_batch_step(md_batch* b, int32_t* steps_run) {
         steps = std::min(steps, b->p.steps_per_launch);
     }
     md_status r;
+    int grid[md::kNumClasses];
+    b->grids(b->p.use_graph != 0, grid);
     if (b->p.use_graph) {
         hipGraphExec_t exec = nullptr;
-        r = b->graph_for(steps, &exec);
+        r = b->graph_for(steps, grid, &exec);
         if (r == MD_OK) r = b->hip(hipGraphLaunch(exec, b->stream), "graph launch");
     } else {
-        r = b->hip(md::launch_batch_steps(b->dev, b->lay.cap, b->lds_cap, b->p.mode, steps, b->stream),
+        r = b->hip(md::launch_batch_steps(b->dev, grid, b->lds_cap, b->p.mode, steps, b->stream),
                    "batch launch");
     }
     if (r != MD_OK) return r;

@@ -120,15 +120,16 @@ constexpr int kRedBlocks = 1024;
 // Batched step.  A batch runs many independent systems through one fixed
 // kernel sequence per step.  Each kernel of the sequence belongs to a block
 // class that fixes how many blocks a system gets in it; a per-class map sends
-// every block of the (fixed, capacity-sized) grid to (slot, block of that
-// system), or to -1 for an idle block.  A block never serves two systems, so a
-// system's arithmetic does not depend on the others in the batch.
+// every block of the grid (at least the blocks in use, at most the class's
+// capacity) to (slot, block of that system), or to -1 for an idle block.  A
+// block never serves two systems, so a system's arithmetic does not depend on
+// the others in the batch.
 // ---------------------------------------------------------------------------
 enum BatchClass {
     kClsParticle = 0,  // ceil(n / kBlock)
     kClsTile,          // ntiles (one block per tile of kTile slots)
     kClsTileScan,      // ceil(ntiles / kBlock): one thread per tile
-    kClsCellSort,      // ceil(ncell * kWave / kBlock): one wavefront per cell
+    kClsCellSort,      // min(ceil(ncell * kWave / kBlock), nblk): wavefronts stride over cells
     kClsSystem,        // 1 (single-workgroup scans)
     kClsVertex,        // LJ: ntiles, patchy: ceil(n / kBlock)
     kClsEdge,          // eblk
@@ -148,7 +149,10 @@ __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
         case kClsParticle: return s.nblk;
         case kClsTile: return s.ntiles;
         case kClsTileScan: return (s.ntiles + kBlock - 1) / kBlock;
-        case kClsCellSort: return (int)(((long long)s.ncell * kWave + kBlock - 1) / kBlock);
+        case kClsCellSort: {  // one wavefront per cell, grid-stride beyond n / kBlock blocks
+            int full = (int)(((long long)s.ncell * kWave + kBlock - 1) / kBlock);
+            return full < s.nblk ? full : s.nblk;
+        }
         case kClsSystem: return 1;
         case kClsVertex: return s.pot == 0 ? s.ntiles : s.nblk;
         default: return s.eblk;
@@ -156,8 +160,10 @@ __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
 }
 
 // Enqueues `steps` batched steps (forces by `mode`) plus the step-count
-// update on `st`; every grid is sized by cap[class], dynamic LDS by lds_cap.
-hipError_t launch_batch_steps(const BatchDev& b, const int* cap, int lds_cap, int mode,
+// update on `st`; the kernels of class c get grid[c] blocks (at most the map
+// capacity of the class, at least the blocks in use), dynamic LDS for regions
+// of lds_cap slots.
+hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int lds_cap, int mode,
                               int steps, hipStream_t st);
 
 // Host-side launchers (md_kernels.hip).  All enqueue on `st`.

@@ -329,18 +329,19 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(Sys s) { b_cell_scatter
 __device__ __forceinline__ void b_cell_sort(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int c = (bid * kBlock + threadIdx.x) / kWave;
-    if (c >= s.ncell) return;
-    const int b = s.cstart[c], m = s.cstart[c + 1] - b;
-    for (int k0 = 0; k0 < m; k0 += kWave) {
-        int p = k0 + lane < m ? s.order[b + k0 + lane] : INT_MAX;
-        int rank = 0;
-        for (int k1 = 0; k1 < m; k1 += kWave) {
-            int o = k1 + lane < m ? s.order[b + k1 + lane] : INT_MAX;
-            int lim = min(kWave, m - k1);
-            for (int l = 0; l < lim; l++) rank += __builtin_amdgcn_readlane(o, l) < p;
+    constexpr int kWaves = kBlock / kWave;
+    for (int c = bid * kWaves + threadIdx.x / kWave; c < s.ncell; c += nb * kWaves) {
+        const int b = s.cstart[c], m = s.cstart[c + 1] - b;
+        for (int k0 = 0; k0 < m; k0 += kWave) {
+            int p = k0 + lane < m ? s.order[b + k0 + lane] : INT_MAX;
+            int rank = 0;
+            for (int k1 = 0; k1 < m; k1 += kWave) {
+                int o = k1 + lane < m ? s.order[b + k1 + lane] : INT_MAX;
+                int lim = min(kWave, m - k1);
+                for (int l = 0; l < lim; l++) rank += __builtin_amdgcn_readlane(o, l) < p;
+            }
+            if (k0 + lane < m) s.rank[b + rank] = p;
         }
-        if (k0 + lane < m) s.rank[b + rank] = p;
     }
 }
 
@@ -1653,11 +1654,11 @@ __global__ __launch_bounds__(kBlock) void kb_advance(BatchDev b, int steps) {
     if (i < b.nslots) b.left[i] = max(0, b.left[i] - steps);
 }
 
-hipError_t launch_batch_steps(const BatchDev& b, const int* cap, int lds_cap, int mode,
+hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int lds_cap, int mode,
                               int steps, hipStream_t st) {
     const size_t sh_pos = 3 * sizeof(double) * (size_t)(lds_cap + 8);
     const size_t sh_map = sizeof(int) * (size_t)(lds_cap + 8);
-    auto g = [&](int cls) { return dim3((unsigned)cap[cls]); };
+    auto g = [&](int cls) { return dim3((unsigned)grid[cls]); };
     const dim3 blk(kBlock), scan(kScanThreads);
     for (int k = 0; k < steps; k++) {
         if (mode == 0) hipLaunchKernelGGL(kb_kick_drift<false>, g(kClsParticle), blk, 0, st, b, k);

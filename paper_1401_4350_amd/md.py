@@ -330,8 +330,12 @@ class Batch:
         return v.value
 
     def retire(self, slot: int) -> System:
-        system = self.systems.pop(slot)
-        self._check(_lib.md_batch_retire(self._h, slot), "md_batch_retire")
+        """Frees the slot and returns its System; raises MDError with the
+        system's device status (the slot is freed all the same) or for a free
+        slot."""
+        st = _lib.md_batch_retire(self._h, slot)
+        system = self.systems.pop(slot, None) if self.steps_left(slot) == -1 else None
+        self._check(st, "md_batch_retire")
         return system
 
     def sync(self):

@@ -288,16 +288,14 @@ class GpuExecutor:
         return [s for s in list(self.batch.systems) if self.batch.steps_left(s) == 0]
 
     def retire(self, slot, cancelled: bool = False) -> dict:
-        g = None
+        g = self.batch.systems.get(slot)
         out: dict = {}
         try:
-            g = self.batch.retire(slot)
+            self.batch.retire(slot)
             out["pairs"] = int(g.stats()["pairs"])
         except self.md.MDError as e:
             out["error"] = str(e)
         finally:
-            if g is None:
-                g = self.batch.systems.pop(slot, None)
             if g is not None:
                 g.close()
         return out
