@@ -38,15 +38,29 @@ def vertex_step_bytes(n: int, pairs: int) -> int:
 
 
 def edge_pass_bytes(n: int, pairs: int) -> int:
-    """Algorithmic bytes of one edge force pass + kick: every half-list entry
-    (4 B), per particle the row start (4 B), its own position (24 B), forces
-    written (24 B) and read back by the kick (24 B), velocity read and written
-    (48 B).  Atomic read-modify-write traffic is not counted here."""
-    return 4 * pairs + 124 * n
+    """Algorithmic bytes of one LJ edge force pass + kick: every half-list
+    entry (partner slot 4 B, region index 2 B), per particle the row start
+    (4 B), its own position (24 B), forces written (24 B) and read back by the
+    kick (24 B), velocity read and written (48 B).  Atomic read-modify-write
+    traffic is not counted here."""
+    return 6 * pairs + 124 * n
 
 
-def time_mode(md, torch, w, state, mode, prec, steps, warmup):
-    g = md.System(md.make_params(w, prec))
+def newton_pass_bytes(n: int, pairs: int, m: int) -> int:
+    """Algorithmic bytes of one Newton-mode pass + kick (LJ): every half-list
+    entry (4 B; with LDS accumulation also its 2 B region index), per
+    particle the row start (4 B), its own position (24 B), velocity read and
+    written (48 B); with m replicas the own force stored (24 B), and the
+    combining pass reading F (24 B), reading and clearing every replica
+    (2 x 32 B each) and writing F (24 B); with LDS accumulation forces
+    written (24 B) and read back by the kick (24 B)."""
+    if m == 0:
+        return 6 * pairs + 124 * n
+    return 4 * pairs + n * (4 + 24 + 48 + 24 + 24 + 64 * m + 24)
+
+
+def time_mode(md, torch, w, state, mode, prec, steps, warmup, newton_m=0):
+    g = md.System(md.make_params(w, prec, newton_m=newton_m))
     g.set_state(state.x, state.v, state.q, state.angmom)
     g.build()
     g.forces(mode)
@@ -246,6 +260,11 @@ def main():
         for mode in ("vertex", "edge"):
             variants[f"{mode}_fp32"] = time_mode(md, torch, w, state, mode, "fp32",
                                                  args.steps, args.warmup)
+    newton = {}
+    if not args.no_variants and w.pot == "lj":
+        for m in (0, 1, 4, 16):
+            newton[m] = time_mode(md, torch, w, state, "newton", args.prec, args.steps,
+                                  args.warmup, newton_m=m)
 
     head = runs["vertex"]
     pairs = head["pairs"]
@@ -269,6 +288,8 @@ def main():
     for k, r in variants.items():
         nbv = (vertex_step_bytes if k.startswith("vertex") else edge_pass_bytes)(w.n, r["pairs"])
         modes[k] = summary(r, nbv)
+    for m, r in newton.items():
+        modes[f"newton_m{m}"] = summary(r, newton_pass_bytes(w.n, r["pairs"], m))
     modes["edge_over_vertex_speedup"] = runs["vertex"]["ms_per_step"] / runs["edge"]["ms_per_step"]
 
     out = {

@@ -3,7 +3,8 @@
  *
  * The engine implements the force step compared in Rovigatti, Sulc, Reguly and
  * Romano, "A comparison between parallelization approaches in molecular
- * dynamics simulations on GPUs", in both of its decompositions:
+ * dynamics simulations on GPUs", in both of its decompositions and the
+ * Newton's-third-law variant the paper weighs against them:
  *
  *   MD_MODE_VERTEX  one thread per particle walks that particle's Verlet list
  *                   and sums every pair itself; each pair is evaluated twice
@@ -14,6 +15,14 @@
  *                   once and adds +F to one particle and -F to the other with
  *                   atomic operations, skipped when the pair force is exactly
  *                   zero (Methods section, "edge-based" approach; Fig. 1 right).
+ *   MD_MODE_NEWTON  the vertex approach with Newton's third law (Discussion
+ *                   section, Fig. S2): the threads of particle i walk its half
+ *                   list (j > i), evaluate each pair once, keep -F for i and add
+ *                   +F to j atomically -- into one of m replicated force arrays
+ *                   that a closing pass sums (md_params.newton_m = m >= 1, as
+ *                   in the paper), or, with newton_m = 0, into a per-workgroup
+ *                   LDS accumulator over the tile's neighbour region that is
+ *                   added to the forces once per workgroup.  LJ only.
  *
  * Both read Verlet lists of radius r_v = r_c + r_s built with a cell algorithm
  * (Methods section), and are followed by an FP64 velocity-Verlet update
@@ -59,7 +68,7 @@ typedef enum {
 } md_status;
 
 typedef enum { MD_POT_LJ = 0, MD_POT_PATCHY = 1 } md_potential;
-typedef enum { MD_MODE_VERTEX = 0, MD_MODE_EDGE = 1 } md_mode;
+typedef enum { MD_MODE_VERTEX = 0, MD_MODE_EDGE = 1, MD_MODE_NEWTON = 2 } md_mode;
 
 /* Arithmetic of the pair forces.  Positions, velocities and the integrator are
  * FP64 in every variant (Methods section, mixed precision). */
@@ -86,6 +95,9 @@ typedef struct {
     double patch_delta;    /* distance of a patch from the particle centre           */
     double patch_rcut;     /* patch-patch cut-off; <= 0 means none                    */
     double inertia;        /* isotropic moment of inertia > 0                        */
+    /* MD_MODE_NEWTON only */
+    int32_t newton_m;      /* replicated force arrays, 1 .. 64; 0: LDS accumulation  */
+    int32_t reserved;      /* must be 0                                              */
 } md_params;
 
 typedef struct {

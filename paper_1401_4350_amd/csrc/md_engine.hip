@@ -17,6 +17,11 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr long long kSlack = 64;  // spare half-list entries
+#ifndef MD_LDS_MARGIN
+#define MD_LDS_MARGIN 1.5
+#endif
+// LDS region capacity of a tile relative to the expected region size
+constexpr double kLdsMargin = MD_LDS_MARGIN;
 
 struct Layout {
     uint64_t state_bytes = 0, ws_bytes = 0;
@@ -24,7 +29,7 @@ struct Layout {
     uint64_t pos, vel, frc, quat, angm, trq, id;
     // workspace offsets
     uint64_t xbuild, tpos, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
-        ncount, hcount, hstart, hj, chunk_row, bsum, epart, wpart, kpart, red, ctrl, tile_seg,
+        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, epart, wpart, kpart, red, ctrl, tile_seg,
         tile_nseg, tile_chunk, tile_nchunk, tile_row0;
     int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
     long long max_half = 0;
@@ -55,6 +60,7 @@ md_status validate(const md_params* p) {
             !fin(p->patch_rcut))
             return MD_ERR_INVALID_ARG;
     }
+    if (p->newton_m < 0 || p->newton_m > 64 || p->reserved != 0) return MD_ERR_INVALID_ARG;
     double rv = p->rcut + p->skin;
     if (!(p->box > 2.0 * rv)) return MD_ERR_BOX_TOO_SMALL;
     // 32-bit slot and half-list indices
@@ -81,12 +87,12 @@ Layout layout(const md_params& p) {
     L.ntiles = (int)((n + md::kTile - 1) / md::kTile);
     {
         // LDS region of a tile: the 3 x 3 rows of cells around its home cells,
-        // about 9 (H + 2) cells of m particles for H home cells; 1.5x margin,
+        // about 9 (H + 2) cells of m particles for H home cells, with a margin;
         // tiles that still do not fit use global gathers.
         double m = (double)n / L.ncell;
         double h = md::kTile / std::max(m, 1e-3) + 1.0;
         double expect = 9.0 * (h + 2.0) * m;
-        int cap = (int)std::ceil(1.5 * expect / 64.0) * 64;
+        int cap = (int)std::ceil(kLdsMargin * expect / 64.0) * 64;
         L.lds_cap = std::min(std::max(cap, 512), md::kLdsCapMax);
     }
     bool patchy = p.pot == MD_POT_PATCHY;
@@ -118,6 +124,8 @@ Layout layout(const md_params& p) {
     L.hcount = take(cur, 4 * n);
     L.hstart = take(cur, 4 * (n + 1));
     L.hj = take(cur, 4 * (uint64_t)L.max_half);
+    L.hr = take(cur, p.pot == MD_POT_LJ ? 2 * (uint64_t)L.max_half : 0);
+    L.rep = take(cur, p.pot == MD_POT_LJ ? 32 * n * (uint64_t)p.newton_m : 0);
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
     L.bsum = take(cur, 4 * (uint64_t)std::max(L.nblk, L.ntiles));  // per-tile half totals
     L.tile_seg = take(cur, 16 * (uint64_t)L.ntiles * md::kSegMax);
@@ -290,6 +298,9 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.hcount = (int*)(W + L.hcount);
     y.hstart = (int*)(W + L.hstart);
     y.hj = (int*)(W + L.hj);
+    y.hr = (uint16_t*)(W + L.hr);
+    y.rep = (double4*)(W + L.rep);
+    y.nrep = p->pot == MD_POT_LJ ? p->newton_m : 0;
     y.chunk_row = (int*)(W + L.chunk_row);
     y.bsum = (int*)(W + L.bsum);
     y.ntiles = L.ntiles;
@@ -313,6 +324,8 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     // One-time clears at creation (never inside a captured step).
     st = s->hip(hipMemsetAsync(y.ccount, 0, 4 * (size_t)L.ncell, s->stream), "clear cell counts");
     if (st == MD_OK) st = s->hip(hipMemsetAsync(d_state, 0, L.state_bytes, s->stream), "clear state");
+    if (st == MD_OK && y.nrep > 0)  // replicas start at zero; the combining pass re-zeroes them
+        st = s->hip(hipMemsetAsync(y.rep, 0, 32 * (size_t)p->n * y.nrep, s->stream), "clear replicas");
     if (st == MD_OK) st = s->hip(md::launch_clear_ctrl(y, s->stream), "clear control");
     if (st == MD_OK) st = s->hip(hipStreamSynchronize(s->stream), "create sync");
     if (st != MD_OK) {
@@ -412,7 +425,10 @@ md_status md_build_neighbors(md_system* s) {
 md_status md_forces(md_system* s, int32_t mode) {
     if (!s) return MD_ERR_INVALID_ARG;
     if (s->batch) return s->admitted();
-    if (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE) return s->fail(MD_ERR_INVALID_ARG, "mode");
+    if (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE && mode != MD_MODE_NEWTON)
+        return s->fail(MD_ERR_INVALID_ARG, "mode");
+    if (mode == MD_MODE_NEWTON && s->p.pot != MD_POT_LJ)
+        return s->fail(MD_ERR_INVALID_ARG, "the Newton mode is implemented for LJ only");
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
     md_status r = s->hip(md::launch_forces(s->sys, mode, s->p.prec, false, s->stream, s->edge_grid),
                          "forces");
@@ -424,15 +440,18 @@ md_status md_forces(md_system* s, int32_t mode) {
 md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     if (!s) return MD_ERR_INVALID_ARG;
     if (s->batch) return s->admitted();
-    if (nsteps < 0 || (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE))
+    if (nsteps < 0 || (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE && mode != MD_MODE_NEWTON))
         return s->fail(MD_ERR_INVALID_ARG, "nsteps/mode");
+    if (mode == MD_MODE_NEWTON && s->p.pot != MD_POT_LJ)
+        return s->fail(MD_ERR_INVALID_ARG, "the Newton mode is implemented for LJ only");
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
     if (!s->forces_valid) {
         md_status r = md_forces(s, mode);
         if (r != MD_OK) return r;
     }
     const md::Sys& y = s->sys;
-    bool edge = mode == MD_MODE_EDGE;
+    // passes that add with atomics into the force array need it cleared first
+    bool edge = mode == MD_MODE_EDGE || (mode == MD_MODE_NEWTON && s->sys.nrep == 0);
     bool prof = s->profiling;
     if (prof) {
         md_status r = s->hip(s->ensure_events(4 * (size_t)nsteps), "profile events");

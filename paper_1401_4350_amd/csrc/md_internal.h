@@ -96,6 +96,9 @@ struct Sys {
     int* hcount;
     int* hstart;     // n + 1
     int* hj;         // half-list partner slots, CSR by row
+    uint16_t* hr;    // LJ: LDS region index of each half-list entry of a staged tile
+    double4* rep;    // Newton mode: nrep replicated force arrays of n records
+    int nrep;
     int* chunk_row;  // first row of every 64-pair chunk of the half list
     int* bsum;       // per-block half counts, then offsets
     int ntiles;      // ceil(n / kTile)
@@ -132,7 +135,7 @@ enum BatchClass {
     kClsCellSort,      // min(ceil(ncell * kWave / kBlock), nblk): wavefronts stride over cells
     kClsSystem,        // 1 (single-workgroup scans)
     kClsVertex,        // LJ: ntiles, patchy: ceil(n / kBlock)
-    kClsEdge,          // eblk
+    kClsEdge,          // LJ: ntiles, patchy: eblk
     kNumClasses
 };
 
@@ -155,7 +158,7 @@ __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
         }
         case kClsSystem: return 1;
         case kClsVertex: return s.pot == 0 ? s.ntiles : s.nblk;
-        default: return s.eblk;
+        default: return s.pot == 0 ? s.ntiles : s.eblk;  // LJ edge: one block per tile
     }
 }
 

@@ -4,10 +4,16 @@
 //
 // Layout: particle records are packed 32-byte double4 (x, y, z, unused) in
 // cell-sorted slot order, so one neighbour gather touches one 32-byte sector;
-// the full Verlet list is ELL column-major (nbr[k * n + i]) so that the k-th
-// entries of consecutive particles are consecutive words (coalesced); the half
-// list is CSR by row.  No kernel here uses matrix cores: the pair step is a
-// gather plus a short scalar formula per pair, not a dense contraction.
+// the full Verlet list is tiled (list_row / list_off): for every tile of 64
+// particles, rows of four entries per particle, so the lanes of a wavefront
+// read consecutive words; the half list is CSR by row.  No kernel here uses
+// matrix cores: the pair step is a gather plus a short scalar formula per
+// pair, not a dense contraction.
+//
+// Every kernel body is a __device__ function of (system, logical block, block
+// count); the single-system __global__ wrappers pass blockIdx (re-indexed per
+// XCD where locality matters) and the batched wrappers (kb_*) pass the block
+// that the batch's block map assigns.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -485,7 +491,7 @@ __device__ __forceinline__ int tile_lds_base(const int4* seg, int nseg, int cb, 
 // ---------------------------------------------------------------------------
 
 constexpr double kFar = 1.0e15;  // coordinate of the padding slot
-__device__ __forceinline__ int lds_plane(int cap) { return cap + 8; }
+__host__ __device__ __forceinline__ int lds_plane(int cap) { return cap + 8; }
 
 struct RegionBatch {
     static constexpr int R = 8;
@@ -779,12 +785,16 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
     for (int m = 0; m < mmax; m++) {
         bool ok = m < mine;
         int ent = ok ? row[list_off(q + m * TPP)] : 0;
-        int j = entry_slot(ent);
-        if (ok && nseg >= 0) j = map[j];  // LDS index -> slot
+        const int reg = entry_slot(ent);
+        int j = reg;
+        if (ok && nseg >= 0) j = map[reg];  // LDS index -> slot
         const bool keep = ok && j > i;
         const unsigned grp = (unsigned)(__ballot(keep) >> gshift) & ((1u << TPP) - 1);
         const long long kk = k + __builtin_popcount(grp & ((1u << q) - 1));
-        if (keep && kk < end) s.hj[kk] = j | (ent & ~kSlotMask);
+        if (keep && kk < end) {
+            s.hj[kk] = j | (ent & ~kSlotMask);
+            if (nseg >= 0) s.hr[kk] = (uint16_t)reg;  // the edge pass accumulates by region
+        }
         k += __builtin_popcount(grp);
     }
 }
@@ -1263,6 +1273,267 @@ __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
 template <int POT, int PREC>
 __global__ __launch_bounds__(kBlock) void k_edge(Sys s) { b_edge<POT, PREC>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
 
+// Adds a staged tile's region accumulator (three planes, like the staged
+// positions) to the global forces: one atomic per non-zero component, the
+// region's slots in runs of consecutive slots (one wavefront per run).
+__device__ __forceinline__ void region_acc_flush(const Sys& s, const double* acc, int plane,
+                                                 int tile, double* F) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nchk = s.tile_nchunk[tile];
+    const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
+    for (int c = threadIdx.x / kWave; c < nchk; c += kBlock / kWave) {
+        const int4 d = chk[c];
+        if (lane < d.y - d.x) {
+            const int r = d.z + lane;
+            const double vx = acc[r], vy = acc[plane + r], vz = acc[2 * plane + r];
+            if ((vx != 0.0) | (vy != 0.0) | (vz != 0.0)) {
+                double* g = F + 4 * (size_t)(d.x + lane);
+                unsafeAtomicAdd(g + 0, vx);
+                unsafeAtomicAdd(g + 1, vy);
+                unsafeAtomicAdd(g + 2, vz);
+            }
+        }
+    }
+}
+
+// LJ edge pass, one workgroup per tile of kTile rows: the tile's half-list
+// entries (contiguous, rows in slot order) are spread over the workgroup's
+// lanes, one entry per lane.  Each lane evaluates its pair once from global
+// positions.  The j side is added with LDS atomics into an accumulator laid
+// out like the tile's staged region (the half list records each entry's
+// region index), the i side is combined per row with a segmented shuffle
+// reduction and added into a per-row LDS accumulator; at the end every
+// non-zero accumulator is added to global memory with one atomic per
+// component, the region in runs of consecutive slots.  Tiles without a staged
+// region add their j side straight to global memory.  Forces must be zero on
+// entry.
+template <int PREC>
+__device__ __forceinline__ void b_edge_lj_tile(const Sys& s, int tile, int nb) {
+    extern __shared__ double acc[];
+    __shared__ int hs[kTile + 1];
+    __shared__ double fi[3 * kTile];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int cap = s.lds_cap;
+    const int plane = lds_plane(cap);
+    const int nseg = s.tile_nseg[tile];
+    const bool staged = nseg >= 0;
+    const int t0 = tile * kTile;
+    const int nrow = min(kTile, s.n - t0);
+    if (staged)
+        for (int k = threadIdx.x; k < 3 * plane; k += kBlock) acc[k] = 0.0;
+    if (threadIdx.x < 3 * kTile) fi[threadIdx.x] = 0.0;
+    if (threadIdx.x <= nrow) hs[threadIdx.x] = s.hstart[t0 + threadIdx.x];
+    __syncthreads();
+    const int e0 = hs[0], e1 = hs[nrow];
+    double* F = reinterpret_cast<double*>(s.frc);
+    for (int base = e0; base < e1; base += kBlock) {
+        const int e = base + threadIdx.x;
+        const bool valid = e < e1;
+        const int es = min(e, e1 - 1);
+        int lo = 0, hi = nrow;  // hs[lo] <= es < hs[hi]
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (hs[mid] <= es) lo = mid;
+            else hi = mid;
+        }
+        const int i = t0 + lo;
+        const int ent = s.hj[es];
+        const int j = min(entry_slot(ent), s.n - 1);
+        const double4 xi = s.pos[i], xj = s.pos[j];
+        const double dx = xj.x - xi.x + image(ent, 0, s.box);
+        const double dy = xj.y - xi.y + image(ent, 1, s.box);
+        const double dz = xj.z - xi.z + image(ent, 2, s.box);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        double fx = 0, fy = 0, fz = 0;
+        if (valid && r2 < s.rc2) {
+            if (PREC == 0) {
+                double fr = lj_fr<double>(r2, s.l64, nullptr);
+                fx = fr * dx;
+                fy = fr * dy;
+                fz = fr * dz;
+            } else {
+                float fr = lj_fr<float>((float)r2, s.l32, nullptr);
+                fx = fr * (float)dx;
+                fy = fr * (float)dy;
+                fz = fr * (float)dz;
+            }
+        }
+        const bool nz = (fx != 0.0) | (fy != 0.0) | (fz != 0.0);
+        if (nz) {
+            if (staged) {
+                const int r = s.hr[es];
+                unsafeAtomicAdd(&acc[r], fx);
+                unsafeAtomicAdd(&acc[plane + r], fy);
+                unsafeAtomicAdd(&acc[2 * plane + r], fz);
+            } else {
+                unsafeAtomicAdd(F + 4 * (size_t)j + 0, fx);
+                unsafeAtomicAdd(F + 4 * (size_t)j + 1, fy);
+                unsafeAtomicAdd(F + 4 * (size_t)j + 2, fz);
+            }
+        }
+        if (__any(nz)) {
+            const int key = valid ? lo : kTile + lane;
+            double sx = seg_sum(-fx, key, lane);
+            double sy = seg_sum(-fy, key, lane);
+            double sz = seg_sum(-fz, key, lane);
+            int up = __shfl_up(key, 1);
+            bool head = valid && (lane == 0 || up != key);
+            if (head && ((sx != 0.0) | (sy != 0.0) | (sz != 0.0))) {
+                unsafeAtomicAdd(&fi[3 * lo + 0], sx);
+                unsafeAtomicAdd(&fi[3 * lo + 1], sy);
+                unsafeAtomicAdd(&fi[3 * lo + 2], sz);
+            }
+        }
+    }
+    __syncthreads();
+    if (staged) region_acc_flush(s, acc, plane, tile, F);
+    if (threadIdx.x < nrow) {
+        const double vx = fi[3 * threadIdx.x], vy = fi[3 * threadIdx.x + 1],
+                     vz = fi[3 * threadIdx.x + 2];
+        if ((vx != 0.0) | (vy != 0.0) | (vz != 0.0)) {
+            double* g = F + 4 * (size_t)(t0 + threadIdx.x);
+            unsafeAtomicAdd(g + 0, vx);
+            unsafeAtomicAdd(g + 1, vy);
+            unsafeAtomicAdd(g + 2, vz);
+        }
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_edge_lj_tile(Sys s) {
+    b_edge_lj_tile<PREC>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Vertex decomposition with Newton's third law (LJ).  The TPP lanes of
+// particle i walk its half list (partners j > i), evaluate each pair once,
+// keep -F_ij for i in registers and add +F_ij to j atomically, skipping exact
+// zeros.  REP: the partner share goes into one of nrep replicated force
+// arrays (chosen per wavefront), i's own sum is stored straight into F (its
+// only writer), and a combining pass adds the replicas to F and clears them.
+// !REP: the partner share of a staged tile goes into an LDS accumulator over
+// the tile's region, added to F once per workgroup (region_acc_flush); i's
+// own sum and unstaged partners are added to F atomically, so F must be zero
+// on entry.
+// ---------------------------------------------------------------------------
+template <int PREC, bool REP>
+__device__ __forceinline__ void b_newton_lj(const Sys& s, int tile, int nb) {
+    extern __shared__ double acc[];
+    constexpr int TPP = kTileTpp;
+    const int cap = s.lds_cap;
+    const int plane = lds_plane(cap);
+    const bool staged = !REP && s.tile_nseg[tile] >= 0;
+    if (!REP) {
+        if (staged)
+            for (int k = threadIdx.x; k < 3 * plane; k += kBlock) acc[k] = 0.0;
+        __syncthreads();
+    }
+    const int i = tile * kTile + threadIdx.x / TPP;
+    const int q = threadIdx.x % TPP;
+    const bool act = i < s.n;
+    const int ii = act ? i : s.n - 1;
+    const int e0 = act ? s.hstart[ii] : 0;
+    const int e1 = act ? s.hstart[ii + 1] : 0;
+    const double4 xi = s.pos[ii];
+    double* F = reinterpret_cast<double*>(s.frc);
+    double* Rp = F;
+    if (REP) {
+        const long long wave = (long long)tile * (kBlock / kWave) + threadIdx.x / kWave;
+        Rp = reinterpret_cast<double*>(s.rep + (size_t)(wave % s.nrep) * s.n);
+    }
+    double fx = 0, fy = 0, fz = 0;
+    for (int e = e0 + q; e < e1; e += TPP) {
+        const int ent = s.hj[e];
+        const int j = min(entry_slot(ent), s.n - 1);
+        const double4 xj = s.pos[j];
+        const double dx = xj.x - xi.x + image(ent, 0, s.box);
+        const double dy = xj.y - xi.y + image(ent, 1, s.box);
+        const double dz = xj.z - xi.z + image(ent, 2, s.box);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < s.rc2) {
+            double gx, gy, gz;  // force on j
+            if (PREC == 0) {
+                double fr = lj_fr<double>(r2, s.l64, nullptr);
+                gx = fr * dx;
+                gy = fr * dy;
+                gz = fr * dz;
+            } else {
+                float fr = lj_fr<float>((float)r2, s.l32, nullptr);
+                gx = fr * (float)dx;
+                gy = fr * (float)dy;
+                gz = fr * (float)dz;
+            }
+            fx -= gx;
+            fy -= gy;
+            fz -= gz;
+            if ((gx != 0.0) | (gy != 0.0) | (gz != 0.0)) {
+                if (staged) {
+                    const int r = s.hr[e];
+                    unsafeAtomicAdd(&acc[r], gx);
+                    unsafeAtomicAdd(&acc[plane + r], gy);
+                    unsafeAtomicAdd(&acc[2 * plane + r], gz);
+                } else {
+                    double* g = Rp + 4 * (size_t)j;
+                    unsafeAtomicAdd(g + 0, gx);
+                    unsafeAtomicAdd(g + 1, gy);
+                    unsafeAtomicAdd(g + 2, gz);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = TPP / 2; off > 0; off >>= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+    }
+    if (act && q == 0) {
+        if (REP) {
+            s.frc[i] = make_double4(fx, fy, fz, 0.0);
+        } else if ((fx != 0.0) | (fy != 0.0) | (fz != 0.0)) {
+            unsafeAtomicAdd(F + 4 * (size_t)i + 0, fx);
+            unsafeAtomicAdd(F + 4 * (size_t)i + 1, fy);
+            unsafeAtomicAdd(F + 4 * (size_t)i + 2, fz);
+        }
+    }
+    if (!REP) {
+        __syncthreads();
+        if (staged) region_acc_flush(s, acc, plane, tile, F);
+    }
+}
+
+template <int PREC, bool REP>
+__global__ __launch_bounds__(kBlock) void k_newton_lj(Sys s) {
+    b_newton_lj<PREC, REP>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Closing pass of the replicated Newton mode: F += sum of the replicas, which
+// are cleared for the next pass; optionally the closing half kick.
+template <bool KICK>
+__global__ __launch_bounds__(kBlock) void k_newton_combine(Sys s) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (KICK && blockIdx.x == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
+    if (i >= s.n) return;
+    double4 f = s.frc[i];
+    for (int r = 0; r < s.nrep; r++) {
+        double4* p = s.rep + (size_t)r * s.n + i;
+        const double4 v = *p;
+        f.x += v.x;
+        f.y += v.y;
+        f.z += v.z;
+        *p = make_double4(0.0, 0.0, 0.0, 0.0);
+    }
+    s.frc[i] = f;
+    if (!isfinite(f.x + f.y + f.z)) atomicOr(&s.ctrl->nonfinite, 1);
+    if (KICK) {
+        double4 v = s.vel[i];
+        v.x += s.hdt * f.x * s.inv_mass;
+        v.y += s.hdt * f.y * s.inv_mass;
+        v.z += s.hdt * f.z * s.inv_mass;
+        s.vel[i] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Velocity Verlet (FP64).  kick_drift: v += dt/2 F/m, x += dt v, wrap into
 // [0, L); patchy also L += dt/2 tau and a free rotation of q by |L|/I dt
@@ -1487,10 +1758,23 @@ static void vertex_dispatch(const Sys& s, bool kick, bool energy, hipStream_t st
 template <int PREC>
 static void edge_dispatch(const Sys& s, int grid, hipStream_t st) {
     dim3 g(grid), b(kBlock);
-    if (s.pot == 0)
-        hipLaunchKernelGGL((k_edge<0, PREC>), g, b, 0, st, s);
-    else
+    if (s.pot == 0) {
+        size_t sh = 3 * sizeof(double) * (size_t)lds_plane(s.lds_cap);
+        hipLaunchKernelGGL((k_edge_lj_tile<PREC>), dim3((unsigned)s.ntiles), b, sh, st, s);
+    } else {
         hipLaunchKernelGGL((k_edge<1, PREC>), g, b, 0, st, s);
+    }
+}
+
+template <int PREC>
+static void newton_dispatch(const Sys& s, hipStream_t st) {
+    dim3 g((unsigned)s.ntiles), b(kBlock);
+    if (s.nrep > 0) {
+        hipLaunchKernelGGL((k_newton_lj<PREC, true>), g, b, 0, st, s);
+    } else {
+        size_t sh = 3 * sizeof(double) * (size_t)lds_plane(s.lds_cap);
+        hipLaunchKernelGGL((k_newton_lj<PREC, false>), g, b, sh, st, s);
+    }
 }
 
 hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_t st, int edge_grid) {
@@ -1498,6 +1782,17 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
         if (prec == 0) vertex_dispatch<0>(s, kick, false, st);
         else if (prec == 1) vertex_dispatch<1>(s, kick, false, st);
         else vertex_dispatch<2>(s, kick, false, st);
+    } else if (mode == 2) {  // Newton (LJ); with atomics into F it must start at zero
+        if (s.nrep == 0 && !kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
+        if (prec == 0) newton_dispatch<0>(s, st);
+        else newton_dispatch<1>(s, st);  // FP32 pair maths, FP64 sums
+        if (s.nrep > 0) {
+            if (kick) hipLaunchKernelGGL(k_newton_combine<true>, grid_n(s.n), dim3(kBlock), 0, st, s);
+            else hipLaunchKernelGGL(k_newton_combine<false>, grid_n(s.n), dim3(kBlock), 0, st, s);
+        } else if (kick) {
+            hipLaunchKernelGGL(k_kick<0>, grid_n(s.n), dim3(kBlock), 0, st, s);
+        }
+        if (!kick) hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
     } else {
         if (!kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) edge_dispatch<0>(s, edge_grid, st);
@@ -1632,8 +1927,8 @@ __global__ __launch_bounds__(kBlock) void kb_vertex(BatchDev b, int step) {
 __global__ __launch_bounds__(kBlock) void kb_edge(BatchDev b, int step) {
     batch_block<kClsEdge>(b, step, [](const Sys& s, int lb) {
         if (s.pot == 0) {
-            if (s.prec == 0) b_edge<0, 0>(s, lb, s.eblk);
-            else b_edge<0, 1>(s, lb, s.eblk);
+            if (s.prec == 0) b_edge_lj_tile<0>(s, lb, s.ntiles);
+            else b_edge_lj_tile<1>(s, lb, s.ntiles);
         } else {
             if (s.prec == 0) b_edge<1, 0>(s, lb, s.eblk);
             else b_edge<1, 1>(s, lb, s.eblk);
@@ -1675,7 +1970,7 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int lds_cap, i
         if (mode == 0) {
             hipLaunchKernelGGL(kb_vertex, g(kClsVertex), blk, sh_pos, st, b, k);
         } else {
-            hipLaunchKernelGGL(kb_edge, g(kClsEdge), blk, 0, st, b, k);
+            hipLaunchKernelGGL(kb_edge, g(kClsEdge), blk, sh_pos, st, b, k);
             hipLaunchKernelGGL(kb_kick, g(kClsParticle), blk, 0, st, b, k);
         }
     }
