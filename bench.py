@@ -79,6 +79,7 @@ def time_mode(md, torch, w, state, mode, prec, steps, warmup, newton_m=0):
     wall = t1 - t0
     return dict(mode=mode, prec=prec, wall_s=wall, ms_per_step=1e3 * wall / steps,
                 pairs=int(st["pairs"]), rebuilds_total=int(st["rebuilds"]),
+                tiles_staged=int(st["tiles_staged"]), tiles_total=int(st["tiles_total"]),
                 force_ms_per_step=prof["force_ms"] / steps,
                 integrate_ms_per_step=prof["integrate_ms"] / steps,
                 rebuild_ms_per_step=prof["rebuild_ms"] / steps,
@@ -281,6 +282,7 @@ def main():
                 "rebuild_us_amortised": 1e3 * r["rebuild_ms_per_step"],
                 "force_pass_GBps": nbytes / (r["force_ms_per_step"] * 1e-3) / 1e9,
                 "pairs": r["pairs"], "list_builds": r["rebuilds_total"],
+                "tiles_staged": r["tiles_staged"], "tiles_total": r["tiles_total"],
                 "energy_per_particle": r["energy_per_particle"]}
 
     modes = {"vertex": summary(runs["vertex"], vertex_step_bytes(w.n, runs["vertex"]["pairs"])),

@@ -679,9 +679,8 @@ BatchLayout batch_layout(const md_batch_params& p) {
     long long c[md::kNumClasses];
     c[md::kClsParticle] = (nmax + md::kBlock - 1) / md::kBlock + smax;
     c[md::kClsTile] = tiles;
-    c[md::kClsTileScan] = (tiles + md::kBlock - 1) / md::kBlock + smax;
+    c[md::kClsScatter] = c[md::kClsParticle] + (tiles + md::kBlock - 1) / md::kBlock + smax;
     c[md::kClsCellSort] = c[md::kClsParticle];  // at most nblk blocks per system
-    c[md::kClsSystem] = smax;
     c[md::kClsVertex] = tiles;
     c[md::kClsEdge] = 4 * tiles;
     uint64_t cur = 0;

@@ -9,7 +9,6 @@ namespace md {
 
 constexpr int kBlock = 256;  // threads per block of the per-particle kernels
 constexpr int kWave = 64;    // CDNA wavefront
-constexpr int kScanThreads = 1024;
 
 // LDS-staged vertex pass: the particles are cut into tiles of kTile
 // consecutive slots; for each tile the list build records up to kSegMax slot
@@ -31,10 +30,12 @@ struct Ctrl {
     int nonfinite;      // sticky: a force or position was NaN/Inf
     int max_count;      // longest full list at the last build
     int staged;         // tiles of the last build whose region fits in LDS
-    int pad0;
+    int done_bin;       // workgroups of the cell binning that have finished
     long long npairs;   // half-list entries at the last build (clamped to capacity)
     long long rebuilds; // number of builds
-    long long pad[4];
+    int done_build;     // workgroups of the list build that have finished
+    int pad1;
+    long long pad[3];
 };
 
 // Pair-potential constants in the arithmetic type of the pair maths.
@@ -129,12 +130,11 @@ constexpr int kRedBlocks = 1024;
 // the others in the batch.
 // ---------------------------------------------------------------------------
 enum BatchClass {
-    kClsParticle = 0,  // ceil(n / kBlock)
+    kClsParticle = 0,  // nblk = ceil(n / kBlock)
     kClsTile,          // ntiles (one block per tile of kTile slots)
-    kClsTileScan,      // ceil(ntiles / kBlock): one thread per tile
+    kClsScatter,       // nblk + ceil(ntiles / kBlock): scatter, then one thread per tile
     kClsCellSort,      // min(ceil(ncell * kWave / kBlock), nblk): wavefronts stride over cells
-    kClsSystem,        // 1 (single-workgroup scans)
-    kClsVertex,        // LJ: ntiles, patchy: ceil(n / kBlock)
+    kClsVertex,        // LJ: ntiles, patchy: nblk
     kClsEdge,          // LJ: ntiles, patchy: eblk
     kNumClasses
 };
@@ -151,12 +151,11 @@ __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
     switch (cls) {
         case kClsParticle: return s.nblk;
         case kClsTile: return s.ntiles;
-        case kClsTileScan: return (s.ntiles + kBlock - 1) / kBlock;
+        case kClsScatter: return s.nblk + (s.ntiles + kBlock - 1) / kBlock;
         case kClsCellSort: {  // one wavefront per cell, grid-stride beyond n / kBlock blocks
             int full = (int)(((long long)s.ncell * kWave + kBlock - 1) / kBlock);
             return full < s.nblk ? full : s.nblk;
         }
-        case kClsSystem: return 1;
         case kClsVertex: return s.pot == 0 ? s.ntiles : s.nblk;
         default: return s.pot == 0 ? s.ntiles : s.eblk;  // LJ edge: one block per tile
     }

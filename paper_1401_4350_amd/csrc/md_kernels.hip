@@ -259,79 +259,137 @@ __global__ void k_clear_ctrl(Ctrl* c) {
     c->overflow = 0;
     c->nonfinite = 0;
     c->max_count = 0;
+    c->staged = 0;
+    c->done_bin = 0;
     c->npairs = 0;
     c->rebuilds = 0;
+    c->done_build = 0;
 }
+
+// True in the one workgroup, of the nb that call this with the same counter,
+// that arrives last; that workgroup then sees the device-scope atomics and
+// agent-scope stores every other one made before arriving.  Resets the
+// counter for its next use.  Every thread of the workgroup must call it.
+__device__ __forceinline__ bool last_block(int* counter, int nb) {
+    __shared__ int is_last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();  // release this workgroup's writes
+        int prev = atomicAdd(counter, 1);
+        is_last = prev == nb - 1;
+        if (is_last) atomicExch(counter, 0);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();  // acquire the others'
+    return true;
+}
+
+
 
 // ---------------------------------------------------------------------------
 // Cell-list counting sort.  Every kernel returns at once unless a rebuild is
 // due, so the sequence can sit in every step without a host round trip.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void b_cell_bin(const Sys& s, int bid, int nb) {
-    if (!s.ctrl->rebuild) return;
-    int p = bid * kBlock + threadIdx.x;
-    if (p >= s.n) return;
-    double4 x = s.pos[p];
-    int cx = cell_coord(wrap_box(x.x, s.box), s.cell_inv, s.nc);
-    int cy = cell_coord(wrap_box(x.y, s.box), s.cell_inv, s.nc);
-    int cz = cell_coord(wrap_box(x.z, s.box), s.cell_inv, s.nc);
-    int c = (cz * s.nc + cy) * s.nc + cx;
-    s.cell[p] = c;
-    s.rank[p] = atomicAdd(&s.ccount[c], 1);
+// Exclusive prefix sum of a[0, len) by one workgroup: emit(k, sum of
+// a[0, k), a[k]) for every k, in chunks of kBlock * 16 elements (each thread
+// sixteen consecutive ones, read as four 16-byte loads; `a` is 16-byte
+// aligned).  Returns the total.
+template <typename Emit>
+__device__ __forceinline__ long long block_scan(const int* a, int len, Emit emit) {
+    constexpr int V = 16;
+    __shared__ long long sh[kBlock];
+    const int t = threadIdx.x;
+    long long base = 0;
+    for (int c0 = 0; c0 < len; c0 += kBlock * V) {
+        const int k0 = c0 + t * V;
+        int v[V];
+        if (k0 + V <= len) {
+            const int4* q = reinterpret_cast<const int4*>(a + k0);
+#pragma unroll
+            for (int u = 0; u < V / 4; u++) {
+                int4 w = q[u];
+                v[4 * u] = w.x;
+                v[4 * u + 1] = w.y;
+                v[4 * u + 2] = w.z;
+                v[4 * u + 3] = w.w;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < V; u++) v[u] = k0 + u < len ? a[k0 + u] : 0;
+        }
+        long long sum = 0;
+#pragma unroll
+        for (int u = 0; u < V; u++) sum += v[u];
+        sh[t] = sum;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            long long w = t >= off ? sh[t - off] : 0;
+            __syncthreads();
+            sh[t] += w;
+            __syncthreads();
+        }
+        long long run = base + sh[t] - sum;
+#pragma unroll
+        for (int u = 0; u < V; u++) {
+            if (k0 + u < len) emit(k0 + u, run, v[u]);
+            run += v[u];
+        }
+        base += sh[kBlock - 1];
+        __syncthreads();  // sh is rewritten by the next chunk
+    }
+    return base;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) { b_cell_bin(s, blockIdx.x, gridDim.x); }
-
-// One workgroup: exclusive scan of the cell counts into cell_start, then the
+// Exclusive scan of the cell counts into cell_start by one workgroup; the
 // counts are cleared for the next build.
-__device__ __forceinline__ void b_cell_scan(const Sys& s, int bid, int nb) {
-    if (!s.ctrl->rebuild) return;
-    __shared__ int sh[kScanThreads];
-    int t = threadIdx.x;
-    int per = (s.ncell + kScanThreads - 1) / kScanThreads;
-    int b = t * per;
-    int e = min(b + per, s.ncell);
-    int sum = 0;
-    for (int k = b; k < e; k++) sum += s.ccount[k];
-    sh[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        int v = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
-    }
-    int run = sh[t] - sum;
-    for (int k = b; k < e; k++) {
-        int c = s.ccount[k];
-        s.cstart[k] = run;
-        run += c;
+__device__ __forceinline__ void scan_cells(const Sys& s) {
+    const long long tot = block_scan(s.ccount, s.ncell, [&](int k, long long run, int) {
+        s.cstart[k] = (int)run;
         s.ccount[k] = 0;
-    }
-    if (t == kScanThreads - 1) s.cstart[s.ncell] = sh[t];
-    if (t == 0) {  // the list build that follows records its maximum and staged tiles
+    });
+    if (threadIdx.x == 0) {
+        s.cstart[s.ncell] = (int)tot;
+        // the list build that follows records its maximum and staged tiles
         s.ctrl->max_count = 0;
         s.ctrl->staged = 0;
     }
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_cell_scan(Sys s) { b_cell_scan(s, blockIdx.x, gridDim.x); }
-
-__device__ __forceinline__ void b_cell_scatter(const Sys& s, int bid, int nb) {
+// Bins every particle into its cell (counts by atomics; the atomic's return
+// value is the particle's provisional rank in the cell); the workgroup that
+// finishes last scans the counts into cell starts.
+__device__ __forceinline__ void b_cell_bin(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
+    const int p = bid * kBlock + threadIdx.x;
+    if (p < s.n) {
+        double4 x = s.pos[p];
+        int cx = cell_coord(wrap_box(x.x, s.box), s.cell_inv, s.nc);
+        int cy = cell_coord(wrap_box(x.y, s.box), s.cell_inv, s.nc);
+        int cz = cell_coord(wrap_box(x.z, s.box), s.cell_inv, s.nc);
+        int c = (cz * s.nc + cy) * s.nc + cx;
+        s.cell[p] = c;
+        s.rank[p] = atomicAdd(&s.ccount[c], 1);
+    }
+    if (last_block(&s.ctrl->done_bin, nb)) scan_cells(s);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) { b_cell_bin(s, blockIdx.x, gridDim.x); }
+
+__device__ __forceinline__ void b_cell_scatter(const Sys& s, int bid) {
     int p = bid * kBlock + threadIdx.x;
     if (p >= s.n) return;
     s.order[s.cstart[s.cell[p]] + s.rank[p]] = p;
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_scatter(Sys s) { b_cell_scatter(s, blockIdx.x, gridDim.x); }
-
 // One wavefront per cell puts the cell's members (scattered in atomic order)
 // in ascending order of their previous slot, so the slot order, and every sum
 // over a list, does not depend on atomic timing.  A member's rank is the
 // number of members with a smaller previous slot, counted with lane reads
-// over the cell (64 members at a time).  The ordered slots go to s.rank.
+// over the cell (64 members at a time).  Each member's records (position
+// wrapped into the box, velocity, id, orientation) are copied to the reorder
+// buffers at its new slot.
 __device__ __forceinline__ void b_cell_sort(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     const int lane = threadIdx.x & (kWave - 1);
@@ -346,29 +404,23 @@ __device__ __forceinline__ void b_cell_sort(const Sys& s, int bid, int nb) {
                 int lim = min(kWave, m - k1);
                 for (int l = 0; l < lim; l++) rank += __builtin_amdgcn_readlane(o, l) < p;
             }
-            if (k0 + lane < m) s.rank[b + rank] = p;
+            if (k0 + lane < m) {  // the particle in previous slot p takes slot b + rank
+                const int q = b + rank;
+                double4 x = s.pos[p];
+                s.tpos[q] = make_double4(wrap_box(x.x, s.box), wrap_box(x.y, s.box),
+                                         wrap_box(x.z, s.box), 0.0);
+                s.tvel[q] = s.vel[p];
+                s.tid[q] = s.id[p];
+                if (s.pot == 1) {
+                    s.tquat[q] = s.quat[p];
+                    s.tangm[q] = s.angm[p];
+                }
+            }
         }
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_sort(Sys s) { b_cell_sort(s, blockIdx.x, gridDim.x); }
-
-__device__ __forceinline__ void b_reorder(const Sys& s, int bid, int nb) {
-    if (!s.ctrl->rebuild) return;
-    int k = bid * kBlock + threadIdx.x;
-    if (k >= s.n) return;
-    int p = s.rank[k];  // previous slot of the particle that takes slot k
-    double4 x = s.pos[p];
-    s.tpos[k] = make_double4(wrap_box(x.x, s.box), wrap_box(x.y, s.box), wrap_box(x.z, s.box), 0.0);
-    s.tvel[k] = s.vel[p];
-    s.tid[k] = s.id[p];
-    if (s.pot == 1) {
-        s.tquat[k] = s.quat[p];
-        s.tangm[k] = s.angm[p];
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_reorder(Sys s) { b_reorder(s, blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------------------
 // Tile regions (one thread per tile of kTile consecutive slots).  The tile's
@@ -390,8 +442,7 @@ __device__ __forceinline__ int cell_of_slot(const int* cstart, int ncell, int sl
     return lo;
 }
 
-__device__ __forceinline__ void b_tiles(const Sys& s, int bid, int nb) {
-    if (!s.ctrl->rebuild) return;
+__device__ __forceinline__ void b_tiles(const Sys& s, int bid) {
     int t = bid * kBlock + threadIdx.x;
     if (t >= s.ntiles) return;
     const int nc = s.nc;
@@ -467,7 +518,17 @@ __device__ __forceinline__ void b_tiles(const Sys& s, int bid, int nb) {
     atomicAdd(&s.ctrl->staged, 1);
 }
 
-__global__ __launch_bounds__(kBlock) void k_tiles(Sys s) { b_tiles(s, blockIdx.x, gridDim.x); }
+// Scatter of the particles into cell order (first nblk workgroups) and the
+// tile regions (the rest); both need only the cell starts.
+__device__ __forceinline__ void b_scatter_tiles(const Sys& s, int bid, int nb) {
+    if (!s.ctrl->rebuild) return;
+    if (bid < s.nblk) b_cell_scatter(s, bid);
+    else b_tiles(s, bid - s.nblk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_tiles(Sys s) {
+    b_scatter_tiles(s, blockIdx.x, gridDim.x);
+}
 
 // Position of slot range [cb, ...) seen through image `code` inside a tile's
 // LDS image: base + (cb - begin) of the segment that holds it, or -1.
@@ -560,6 +621,20 @@ __device__ __forceinline__ void region_finish(const Sys& s, const double4* src, 
 // lengths (entries with j > i) feed the half-list offsets.
 // ---------------------------------------------------------------------------
 
+// Exclusive scan of the per-tile half-list totals into tile offsets by one
+// workgroup (the last of the list build); records |E| and the build count.
+__device__ __forceinline__ void scan_tiles(const Sys& s) {
+    const long long cap = s.max_half;
+    const long long tot = block_scan(s.bsum, s.ntiles, [&](int k, long long run, int) {
+        s.bsum[k] = (int)(run < cap ? run : cap);
+    });
+    if (threadIdx.x == 0) {
+        s.ctrl->npairs = tot < cap ? tot : cap;
+        if (tot > cap) atomicOr(&s.ctrl->overflow, 1);
+        s.ctrl->rebuilds += 1;
+    }
+}
+
 __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     extern __shared__ double lds[];
@@ -612,13 +687,28 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
             int ay = cy + lo + dy;
             int wy = ay < 0 ? 0 : (ay >= nc ? 2 : 1);
             ay = ay < 0 ? ay + nc : (ay >= nc ? ay - nc : ay);
-            for (int dx = 0; dx < span; dx++) {
-                int ax = cx + lo + dx;
-                int wx = ax < 0 ? 0 : (ax >= nc ? 2 : 1);
-                ax = ax < 0 ? ax + nc : (ax >= nc ? ax - nc : ax);
-                const int c = (az * nc + ay) * nc + ax;
-                const int cb = act ? s.cstart[c] : 0;
-                const int ce = act ? s.cstart[c + 1] : 0;
+            // The neighbour cells of this row in list order (dx ascending) as
+            // runs of consecutive cells, i.e. of consecutive slots: one run
+            // (cx - 1 .. cx + 1), or two where the row wraps the box; for
+            // nc < 3 every distinct cell on its own.
+            int a0, b0, w0, a1 = 0, b1 = 0, w1 = 1, nr;
+            if (nc >= 3) {
+                if (cx == 0) {
+                    a0 = b0 = nc - 1, w0 = 0, a1 = 0, b1 = 1, nr = 2;
+                } else if (cx == nc - 1) {
+                    a0 = nc - 2, b0 = nc - 1, w0 = 1, a1 = b1 = 0, w1 = 2, nr = 2;
+                } else {
+                    a0 = cx - 1, b0 = cx + 1, w0 = 1, nr = 1;
+                }
+            } else {
+                a0 = b0 = cx, w0 = 1, nr = nc;
+                if (nc == 2) a1 = b1 = 1 - cx, w1 = cx == 1 ? 2 : 1;
+            }
+            const int rowbase = (az * nc + ay) * nc;
+            for (int run = 0; run < nr; run++) {
+                const int xa = run ? a1 : a0, xb = run ? b1 : b0, wx = run ? w1 : w0;
+                const int cb = act ? s.cstart[rowbase + xa] : 0;
+                const int ce = act ? s.cstart[rowbase + xb + 1] : 0;
                 const int code = wx | wy << 2 | wz << 4;
                 int base = -1;
                 if (nseg >= 0 && cb < ce) {
@@ -660,12 +750,17 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                     const int k = count + __builtin_popcount(grp & ((1u << q) - 1));
                     if (keep && k < s.cap) row[list_off(k)] = ent;
                     // half entries among the stored ones (k < cap)
-                    for (int l = 0; l < TPP; l++)
-                        if ((balh >> l) & 1) {
-                            int kl = count + __builtin_popcount(grp & ((1u << l) - 1));
-                            half += kl < s.cap;
-                        }
-                    count += __builtin_popcount(grp);
+                    const int nk = __builtin_popcount(grp);
+                    if (count + nk <= s.cap) {
+                        half += __builtin_popcount(balh);
+                    } else {
+                        for (int l = 0; l < TPP; l++)
+                            if ((balh >> l) & 1) {
+                                int kl = count + __builtin_popcount(grp & ((1u << l) - 1));
+                                half += kl < s.cap;
+                            }
+                    }
+                    count += nk;
                 }
             }
         }
@@ -686,43 +781,11 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
         for (int w = 0; w < kBlock / kWave; w++) t += red[w];
         s.bsum[tile] = t;
     }
+    if (last_block(&s.ctrl->done_build, nb)) scan_tiles(s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_build(Sys s) { b_build(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
 
-// One workgroup: exclusive scan of the per-tile half totals.
-__device__ __forceinline__ void b_half_scan(const Sys& s, int bid, int nb) {
-    if (!s.ctrl->rebuild) return;
-    __shared__ long long sh[kScanThreads];
-    int t = threadIdx.x;
-    int per = (s.ntiles + kScanThreads - 1) / kScanThreads;
-    int b = t * per;
-    int e = min(b + per, s.ntiles);
-    long long sum = 0;
-    for (int k = b; k < e; k++) sum += s.bsum[k];
-    sh[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        long long v = t >= off ? sh[t - off] : 0;
-        __syncthreads();
-        sh[t] += v;
-        __syncthreads();
-    }
-    long long run = sh[t] - sum;
-    for (int k = b; k < e; k++) {
-        int c = s.bsum[k];
-        s.bsum[k] = (int)(run < s.max_half ? run : s.max_half);
-        run += c;
-    }
-    if (t == kScanThreads - 1) {
-        long long tot = sh[t];
-        s.ctrl->npairs = tot < s.max_half ? tot : s.max_half;
-        if (tot > s.max_half) atomicOr(&s.ctrl->overflow, 1);
-        s.ctrl->rebuilds += 1;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_half_scan(Sys s) { b_half_scan(s, blockIdx.x, gridDim.x); }
 
 // Half list (edge pass): one workgroup per tile, four lanes per particle.
 // Row starts are the tile offset plus a prefix over the tile's particles; a
@@ -1698,20 +1761,19 @@ hipError_t launch_clear_ctrl(const Sys& s, hipStream_t st) {
 }
 
 hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) {
+    // cells: bin (+ scan by the last workgroup), scatter + tile regions, sort +
+    // reorder; lists: build (+ half-list scan by the last workgroup), half fill
     if (cells) {
         hipLaunchKernelGGL(k_cell_bin, grid_n(s.n), dim3(kBlock), 0, st, s);
-        hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(kScanThreads), 0, st, s);
-        hipLaunchKernelGGL(k_cell_scatter, grid_n(s.n), dim3(kBlock), 0, st, s);
+        hipLaunchKernelGGL(k_scatter_tiles, dim3((unsigned)class_blocks(s, kClsScatter)),
+                           dim3(kBlock), 0, st, s);
         hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)(((long long)s.ncell * kWave + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, st, s);
-        hipLaunchKernelGGL(k_reorder, grid_n(s.n), dim3(kBlock), 0, st, s);
     }
     if (lists) {
-        hipLaunchKernelGGL(k_tiles, grid_n(s.ntiles), dim3(kBlock), 0, st, s);
         size_t sh_pos = 3 * sizeof(double) * (size_t)(s.lds_cap + 8);
         size_t sh_map = sizeof(int) * (size_t)(s.lds_cap + 8);
         hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), sh_pos, st, s);
-        hipLaunchKernelGGL(k_half_scan, dim3(1), dim3(kScanThreads), 0, st, s);
         hipLaunchKernelGGL(k_half_fill, dim3(s.ntiles), dim3(kBlock), sh_map, st, s);
     }
     return hipGetLastError();
@@ -1871,12 +1933,10 @@ __global__ __launch_bounds__(kBlock) void kb_cell_bin(BatchDev b, int step) {
     batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_cell_bin(s, lb, s.nblk); });
 }
 
-__global__ __launch_bounds__(kScanThreads) void kb_cell_scan(BatchDev b, int step) {
-    batch_block<kClsSystem>(b, step, [](const Sys& s, int lb) { b_cell_scan(s, lb, 1); });
-}
-
-__global__ __launch_bounds__(kBlock) void kb_cell_scatter(BatchDev b, int step) {
-    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_cell_scatter(s, lb, s.nblk); });
+__global__ __launch_bounds__(kBlock) void kb_scatter_tiles(BatchDev b, int step) {
+    batch_block<kClsScatter>(b, step, [](const Sys& s, int lb) {
+        b_scatter_tiles(s, lb, class_blocks(s, kClsScatter));
+    });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_cell_sort(BatchDev b, int step) {
@@ -1885,22 +1945,8 @@ __global__ __launch_bounds__(kBlock) void kb_cell_sort(BatchDev b, int step) {
     });
 }
 
-__global__ __launch_bounds__(kBlock) void kb_reorder(BatchDev b, int step) {
-    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_reorder(s, lb, s.nblk); });
-}
-
-__global__ __launch_bounds__(kBlock) void kb_tiles(BatchDev b, int step) {
-    batch_block<kClsTileScan>(b, step, [](const Sys& s, int lb) {
-        b_tiles(s, lb, class_blocks(s, kClsTileScan));
-    });
-}
-
 __global__ __launch_bounds__(kBlock) void kb_build(BatchDev b, int step) {
     batch_block<kClsTile>(b, step, [](const Sys& s, int lb) { b_build(s, lb, s.ntiles); });
-}
-
-__global__ __launch_bounds__(kScanThreads) void kb_half_scan(BatchDev b, int step) {
-    batch_block<kClsSystem>(b, step, [](const Sys& s, int lb) { b_half_scan(s, lb, 1); });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_half_fill(BatchDev b, int step) {
@@ -1954,18 +2000,14 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int lds_cap, i
     const size_t sh_pos = 3 * sizeof(double) * (size_t)(lds_cap + 8);
     const size_t sh_map = sizeof(int) * (size_t)(lds_cap + 8);
     auto g = [&](int cls) { return dim3((unsigned)grid[cls]); };
-    const dim3 blk(kBlock), scan(kScanThreads);
+    const dim3 blk(kBlock);
     for (int k = 0; k < steps; k++) {
         if (mode == 0) hipLaunchKernelGGL(kb_kick_drift<false>, g(kClsParticle), blk, 0, st, b, k);
         else hipLaunchKernelGGL(kb_kick_drift<true>, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_cell_bin, g(kClsParticle), blk, 0, st, b, k);
-        hipLaunchKernelGGL(kb_cell_scan, g(kClsSystem), scan, 0, st, b, k);
-        hipLaunchKernelGGL(kb_cell_scatter, g(kClsParticle), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_scatter_tiles, g(kClsScatter), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_cell_sort, g(kClsCellSort), blk, 0, st, b, k);
-        hipLaunchKernelGGL(kb_reorder, g(kClsParticle), blk, 0, st, b, k);
-        hipLaunchKernelGGL(kb_tiles, g(kClsTileScan), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_build, g(kClsTile), blk, sh_pos, st, b, k);
-        hipLaunchKernelGGL(kb_half_scan, g(kClsSystem), scan, 0, st, b, k);
         hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
         if (mode == 0) {
             hipLaunchKernelGGL(kb_vertex, g(kClsVertex), blk, sh_pos, st, b, k);
