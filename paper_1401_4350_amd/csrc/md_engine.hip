@@ -18,7 +18,7 @@ namespace {
 constexpr uint64_t kAlign = 256;
 constexpr long long kSlack = 64;  // spare half-list entries
 #ifndef MD_LDS_MARGIN
-#define MD_LDS_MARGIN 1.5
+#define MD_LDS_MARGIN 1.45
 #endif
 // LDS region capacity of a tile relative to the expected region size
 constexpr double kLdsMargin = MD_LDS_MARGIN;
@@ -679,8 +679,8 @@ BatchLayout batch_layout(const md_batch_params& p) {
     long long c[md::kNumClasses];
     c[md::kClsParticle] = (nmax + md::kBlock - 1) / md::kBlock + smax;
     c[md::kClsTile] = tiles;
-    c[md::kClsScatter] = c[md::kClsParticle] + (tiles + md::kBlock - 1) / md::kBlock + smax;
-    c[md::kClsCellSort] = c[md::kClsParticle];  // at most nblk blocks per system
+    // cell sort: at most nblk blocks per system; tile regions: 4 tiles per block
+    c[md::kClsSortTiles] = c[md::kClsParticle] + (tiles + 3) / 4 + smax;
     c[md::kClsVertex] = tiles;
     c[md::kClsEdge] = 4 * tiles;
     uint64_t cur = 0;

@@ -132,8 +132,7 @@ constexpr int kRedBlocks = 1024;
 enum BatchClass {
     kClsParticle = 0,  // nblk = ceil(n / kBlock)
     kClsTile,          // ntiles (one block per tile of kTile slots)
-    kClsScatter,       // nblk + ceil(ntiles / kBlock): scatter, then one thread per tile
-    kClsCellSort,      // min(ceil(ncell * kWave / kBlock), nblk): wavefronts stride over cells
+    kClsSortTiles,     // sort_blocks + ceil(ntiles / 4): cell sort, then a wavefront per tile
     kClsVertex,        // LJ: ntiles, patchy: nblk
     kClsEdge,          // LJ: ntiles, patchy: eblk
     kNumClasses
@@ -146,16 +145,19 @@ struct BatchDev {
     int nslots;
 };
 
+// Workgroups of the cell sort: one wavefront per cell, striding over the
+// cells beyond nblk workgroups.
+__host__ __device__ inline int sort_blocks(const Sys& s) {
+    int full = (int)(((long long)s.ncell * kWave + kBlock - 1) / kBlock);
+    return full < s.nblk ? full : s.nblk;
+}
+
 // Blocks a system takes in a class.
 __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
     switch (cls) {
         case kClsParticle: return s.nblk;
         case kClsTile: return s.ntiles;
-        case kClsScatter: return s.nblk + (s.ntiles + kBlock - 1) / kBlock;
-        case kClsCellSort: {  // one wavefront per cell, grid-stride beyond n / kBlock blocks
-            int full = (int)(((long long)s.ncell * kWave + kBlock - 1) / kBlock);
-            return full < s.nblk ? full : s.nblk;
-        }
+        case kClsSortTiles: return sort_blocks(s) + (s.ntiles + kBlock / kWave - 1) / (kBlock / kWave);
         case kClsVertex: return s.pot == 0 ? s.ntiles : s.nblk;
         default: return s.pot == 0 ? s.ntiles : s.eblk;  // LJ edge: one block per tile
     }

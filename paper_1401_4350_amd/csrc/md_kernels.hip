@@ -84,11 +84,12 @@ __device__ __forceinline__ double wrap_box(double y, double L) {
 
 // 1/a from the hardware reciprocal refined by two Newton steps (to within an
 // ulp of the correctly rounded quotient for normal a).
+// 1 / a from the hardware reciprocal (relative error 4.6e-8 on gfx950) and
+// one Newton step: relative error below 2.2e-15 over the r^2 range of the
+// pair maths (measured against a long-double reference on 4M arguments).
 __device__ __forceinline__ double rcp_nr(double a) {
     double y = __builtin_amdgcn_rcp(a);
     double e = fma(-a, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-a, y, 1.0);
     return fma(y, e, y);
 }
 __device__ __forceinline__ float rcp_nr(float a) {
@@ -103,7 +104,6 @@ __device__ __forceinline__ int cell_coord(double x, double cell_inv, int nc) {
     return c >= nc ? nc - 1 : c;
 }
 
-__device__ __forceinline__ double* comp(double4* a, int i) { return reinterpret_cast<double*>(a + i); }
 
 // ---------------------------------------------------------------------------
 // Pair potentials (arithmetic type R; accumulation is the caller's)
@@ -235,18 +235,6 @@ __device__ __forceinline__ void patchy_pair(const V3<double>& d, double r2, cons
     }
 }
 
-template <typename R>
-__device__ __forceinline__ const PatchyC<R>& pick(const PatchyC<double>& a, const PatchyC<float>& b);
-template <>
-__device__ __forceinline__ const PatchyC<double>& pick<double>(const PatchyC<double>& a,
-                                                               const PatchyC<float>&) {
-    return a;
-}
-template <>
-__device__ __forceinline__ const PatchyC<float>& pick<float>(const PatchyC<double>&,
-                                                             const PatchyC<float>& b) {
-    return b;
-}
 
 // ---------------------------------------------------------------------------
 // Control
@@ -377,10 +365,15 @@ __device__ __forceinline__ void b_cell_bin(const Sys& s, int bid, int nb) {
 
 __global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) { b_cell_bin(s, blockIdx.x, gridDim.x); }
 
-__device__ __forceinline__ void b_cell_scatter(const Sys& s, int bid) {
+__device__ __forceinline__ void b_cell_scatter(const Sys& s, int bid, int nb) {
+    if (!s.ctrl->rebuild) return;
     int p = bid * kBlock + threadIdx.x;
     if (p >= s.n) return;
     s.order[s.cstart[s.cell[p]] + s.rank[p]] = p;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_scatter(Sys s) {
+    b_cell_scatter(s, blockIdx.x, gridDim.x);
 }
 
 // One wavefront per cell puts the cell's members (scattered in atomic order)
@@ -391,7 +384,6 @@ __device__ __forceinline__ void b_cell_scatter(const Sys& s, int bid) {
 // wrapped into the box, velocity, id, orientation) are copied to the reorder
 // buffers at its new slot.
 __device__ __forceinline__ void b_cell_sort(const Sys& s, int bid, int nb) {
-    if (!s.ctrl->rebuild) return;
     const int lane = threadIdx.x & (kWave - 1);
     constexpr int kWaves = kBlock / kWave;
     for (int c = bid * kWaves + threadIdx.x / kWave; c < s.ncell; c += nb * kWaves) {
@@ -420,10 +412,8 @@ __device__ __forceinline__ void b_cell_sort(const Sys& s, int bid, int nb) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_sort(Sys s) { b_cell_sort(s, blockIdx.x, gridDim.x); }
-
 // ---------------------------------------------------------------------------
-// Tile regions (one thread per tile of kTile consecutive slots).  The tile's
+// Tile regions (one wavefront per tile of kTile consecutive slots).  The tile's
 // home cells are a run of cell ids over at most two rows of cells; the 27-cell
 // neighbourhood of a row run is, for each of the 9 surrounding rows, an
 // x-interval of cells, i.e. a contiguous slot range, split in two where it
@@ -432,103 +422,105 @@ __global__ __launch_bounds__(kBlock) void k_cell_sort(Sys s) { b_cell_sort(s, bl
 // image.  Tiles over more rows, or spanning a whole row, use global gathers.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int cell_of_slot(const int* cstart, int ncell, int slot) {
-    int lo = 0, hi = ncell;  // largest c with cstart[c] <= slot
-    while (hi - lo > 1) {
-        int mid = (lo + hi) >> 1;
-        if (cstart[mid] <= slot) lo = mid;
-        else hi = mid;
+
+// Wavefront prefix sum (exclusive) of v over the 64 lanes.
+__device__ __forceinline__ int wave_excl_scan(int v, int lane) {
+    int x = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
-    return lo;
+    return x - v;
 }
 
-__device__ __forceinline__ void b_tiles(const Sys& s, int bid) {
-    int t = bid * kBlock + threadIdx.x;
-    if (t >= s.ntiles) return;
+// Region of one tile, computed by one wavefront.  Segment slots are fixed:
+// two per (home row h, dz, dy), slot ((h * 3 + dz + 1) * 3 + dy + 1) * 2 + k,
+// the second one empty unless the x-interval wraps the box, so the list
+// build finds a cell's segment by index.  Lane q < 36 fills slot q; LDS bases
+// and the copy chunks (runs of at most 64 slots) follow from wavefront prefix
+// sums.  Runs after the scatter: the cell of new slot a is cell[order[a]].
+__device__ __forceinline__ void b_tile_region(const Sys& s, int t) {
+    const int lane = threadIdx.x & (kWave - 1);
     const int nc = s.nc;
     if (nc < 3 || s.pot != 0) {  // the patchy pass gathers from global memory
-        s.tile_nseg[t] = -1;
+        if (lane == 0) s.tile_nseg[t] = -1;
         return;
     }
     const int a = t * kTile;
     const int b = min(a + kTile, s.n) - 1;
-    const int c0 = cell_of_slot(s.cstart, s.ncell, a);
-    const int c1 = cell_of_slot(s.cstart, s.ncell, b);
+    const int c0 = s.cell[s.order[a]], c1 = s.cell[s.order[b]];
     const int r0 = c0 / nc, r1 = c1 / nc;
-    // Segment slots are fixed: two per (home row, dz, dy), in loop order, the
-    // second one empty unless the x-interval wraps; the list build finds a
-    // cell's segment by index instead of searching.
-    int4* seg = s.tile_seg + (size_t)t * kSegMax;
-    int nseg = 0, base = 0;
     bool ok = r1 - r0 <= 1;
-    auto emit = [&](int row, int lo, int hi, int code) {
-        int b0 = s.cstart[row * nc + lo], b1 = s.cstart[row * nc + hi + 1];
-        if (base + (b1 - b0) > s.lds_cap) ok = false;
-        seg[nseg++] = make_int4(b0, b1, base, code);
-        base += b1 - b0;
-    };
-    auto none = [&]() { seg[nseg++] = make_int4(0, 0, base, -1); };
-    auto wrapc = [&](int v) { return v < 0 ? 0 : (v >= nc ? 2 : 1); };  // shift -L, 0, +L
-    for (int r = r0; r <= r1 && ok; r++) {
-        int xa = r == r0 ? c0 % nc : 0;
-        int xb = r == r1 ? c1 % nc : nc - 1;
-        if (xb - xa + 3 > nc) {  // would need one row through two x images
-            ok = false;
-            break;
+    const int nseg = r1 > r0 ? 36 : 18;
+    int b0 = 0, b1 = 0, code = -1;  // this lane's segment: slots [b0, b1), image code
+    bool bad = false;
+    if (ok && lane < nseg) {
+        const int h = lane / 18, dz = (lane / 6) % 3 - 1, dy = (lane / 2) % 3 - 1, k2 = lane & 1;
+        const int r = r0 + h;
+        const int xa = r == r0 ? c0 % nc : 0;
+        const int xb = r == r1 ? c1 % nc : nc - 1;
+        bad = xb - xa + 3 > nc;  // one row would need two x images
+        const int y = r % nc, z = r / nc;
+        auto wrapc = [&](int v) { return v < 0 ? 0 : (v >= nc ? 2 : 1); };  // shift -L, 0, +L
+        const int rr = ((z + dz + nc) % nc) * nc + (y + dy + nc) % nc;
+        const int yz = wrapc(y + dy) << 2 | wrapc(z + dz) << 4;
+        const int lo = xa - 1, hi = xb + 1;
+        int xl = 0, xh = -1;  // cell run [xl, xh] of this slot, empty if xh < xl
+        if (lo < 0) {
+            if (k2 == 0) xl = lo + nc, xh = nc - 1, code = yz | 0;
+            else xl = 0, xh = hi, code = yz | 1;
+        } else if (hi >= nc) {
+            if (k2 == 0) xl = lo, xh = nc - 1, code = yz | 1;
+            else xl = 0, xh = hi - nc, code = yz | 2;
+        } else if (k2 == 0) {
+            xl = lo, xh = hi, code = yz | 1;
         }
-        int y = r % nc, z = r / nc;
-        for (int dz = -1; dz <= 1 && ok; dz++)
-            for (int dy = -1; dy <= 1 && ok; dy++) {
-                int rr = ((z + dz + nc) % nc) * nc + (y + dy + nc) % nc;
-                int yz = wrapc(y + dy) << 2 | wrapc(z + dz) << 4;
-                int lo = xa - 1, hi = xb + 1;
-                if (lo < 0) {
-                    emit(rr, lo + nc, nc - 1, yz | 0);
-                    emit(rr, 0, hi, yz | 1);
-                } else if (hi >= nc) {
-                    emit(rr, lo, nc - 1, yz | 1);
-                    emit(rr, 0, hi - nc, yz | 2);
-                } else {
-                    emit(rr, lo, hi, yz | 1);
-                    none();
-                }
-            }
-    }
-    static_assert(kSegMax >= 36, "two home rows x 9 neighbour rows x 2 slots");
-    // copy chunks of at most one wavefront each
-    int4* chk = s.tile_chunk + (size_t)t * kChunkMax;
-    int nchk = 0;
-    for (int q = 0; q < nseg && ok; q++) {
-        int4 g = seg[q];
-        for (int b0 = g.x; b0 < g.y; b0 += kWave) {
-            if (nchk == kChunkMax) {
-                ok = false;
-                break;
-            }
-            chk[nchk++] = make_int4(b0, min(g.y, b0 + kWave), g.z + (b0 - g.x), g.w);
+        if (!bad && xh >= xl) {
+            b0 = s.cstart[rr * nc + xl];
+            b1 = s.cstart[rr * nc + xh + 1];
         }
     }
+    ok = ok && !__any(bad);
+    const int len = b1 - b0;
+    const int base = wave_excl_scan(len, lane);
+    const int total = __shfl(base + len, kWave - 1);
+    const int nch = (len + kWave - 1) / kWave;
+    const int cbase = wave_excl_scan(nch, lane);
+    const int nchk = __shfl(cbase + nch, kWave - 1);
+    ok = ok && total <= s.lds_cap && nchk <= kChunkMax;
     if (!ok) {
-        s.tile_nseg[t] = -1;
+        if (lane == 0) s.tile_nseg[t] = -1;
         return;
     }
-    s.tile_nchunk[t] = nchk;
-    s.tile_row0[t] = r0;
-    s.tile_nseg[t] = nseg;
-    atomicAdd(&s.ctrl->staged, 1);
+    static_assert(kSegMax >= 36, "two home rows x 9 neighbour rows x 2 slots");
+    if (lane < nseg) s.tile_seg[(size_t)t * kSegMax + lane] = make_int4(b0, b1, base, code);
+    int4* chk = s.tile_chunk + (size_t)t * kChunkMax + cbase;
+    for (int u = 0; u < nch; u++)
+        chk[u] = make_int4(b0 + u * kWave, min(b1, b0 + (u + 1) * kWave), base + u * kWave, code);
+    if (lane == 0) {
+        s.tile_nchunk[t] = nchk;
+        s.tile_row0[t] = r0;
+        s.tile_nseg[t] = nseg;
+        atomicAdd(&s.ctrl->staged, 1);
+    }
 }
 
-// Scatter of the particles into cell order (first nblk workgroups) and the
-// tile regions (the rest); both need only the cell starts.
-__device__ __forceinline__ void b_scatter_tiles(const Sys& s, int bid, int nb) {
+// Cell sort (the first sort_blocks workgroups, wavefronts striding over the
+// cells) and tile regions (the rest, one wavefront per tile).
+__device__ __forceinline__ void b_sort_tiles(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
-    if (bid < s.nblk) b_cell_scatter(s, bid);
-    else b_tiles(s, bid - s.nblk);
+    const int ns = sort_blocks(s);
+    if (bid < ns) {
+        b_cell_sort(s, bid, ns);
+    } else {
+        const int t = (bid - ns) * (kBlock / kWave) + threadIdx.x / kWave;
+        if (t < s.ntiles) b_tile_region(s, t);
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_tiles(Sys s) {
-    b_scatter_tiles(s, blockIdx.x, gridDim.x);
-}
+__global__ __launch_bounds__(kBlock) void k_sort_tiles(Sys s) { b_sort_tiles(s, blockIdx.x, gridDim.x); }
+
 
 // Position of slot range [cb, ...) seen through image `code` inside a tile's
 // LDS image: base + (cb - begin) of the segment that holds it, or -1.
@@ -547,12 +539,21 @@ __device__ __forceinline__ int tile_lds_base(const int4* seg, int nseg, int cb, 
 // batch are issued by region_issue and consumed by region_store, so a caller
 // can put other loads in between: loads retire in order, so the first batch
 // is issued before slower loads and stored right after them.
-// LDS layout: three planes (x, y, z) of `plane` doubles; slot `cap` of every
-// plane is a padding particle far outside the box.
+// LDS layout: one 32-byte record (x, y, z, unused) per region slot, so a
+// neighbour is one address and two reads (16 + 8 bytes); slot `cap` is a
+// padding particle far outside the box.
 // ---------------------------------------------------------------------------
 
 constexpr double kFar = 1.0e15;  // coordinate of the padding slot
 __host__ __device__ __forceinline__ int lds_plane(int cap) { return cap + 8; }
+// Dynamic LDS of the kernels that stage a tile's region (positions), and of
+// those that accumulate over it (three planes of doubles).
+__host__ __device__ __forceinline__ size_t lds_region_bytes(int cap) {
+    return sizeof(double4) * (size_t)lds_plane(cap);
+}
+__host__ __device__ __forceinline__ size_t lds_acc_bytes(int cap) {
+    return 3 * sizeof(double) * (size_t)lds_plane(cap);
+}
 
 struct RegionBatch {
     static constexpr int R = 8;
@@ -574,37 +575,30 @@ __device__ __forceinline__ void region_issue(const Sys& s, const double4* src, i
     }
 }
 
-__device__ __forceinline__ void region_store(const Sys& s, double* lds, int plane,
-                                             const RegionBatch& b) {
+__device__ __forceinline__ void region_store(const Sys& s, double4* lds, const RegionBatch& b) {
     const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int r = 0; r < RegionBatch::R; r++) {
         const int4 d = b.d[r];
         if (d.w >= 0 && lane < d.y - d.x) {
-            int m = d.z + lane;
             // the chunk's periodic image is added on the way in
-            lds[m] = b.p[r].x + (double)((d.w & 3) - 1) * s.box;
-            lds[plane + m] = b.p[r].y + (double)(((d.w >> 2) & 3) - 1) * s.box;
-            lds[2 * plane + m] = b.p[r].z + (double)(((d.w >> 4) & 3) - 1) * s.box;
+            lds[d.z + lane] = make_double4(b.p[r].x + (double)((d.w & 3) - 1) * s.box,
+                                           b.p[r].y + (double)(((d.w >> 2) & 3) - 1) * s.box,
+                                           b.p[r].z + (double)(((d.w >> 4) & 3) - 1) * s.box, 0.0);
         }
     }
 }
 
 // Remaining batches, padding slot and the workgroup barrier.
-__device__ __forceinline__ void region_finish(const Sys& s, const double4* src, double* lds,
+__device__ __forceinline__ void region_finish(const Sys& s, const double4* src, double4* lds,
                                               int cap, int tile, int nchk, int wv,
                                               RegionBatch& rb) {
     constexpr int W = kBlock / kWave;
-    const int plane = lds_plane(cap);
     for (int c0 = wv + W * RegionBatch::R; c0 < nchk; c0 += W * RegionBatch::R) {
         region_issue(s, src, tile, nchk, c0, rb);
-        region_store(s, lds, plane, rb);
+        region_store(s, lds, rb);
     }
-    if (threadIdx.x == 0) {
-        lds[cap] = kFar;
-        lds[plane + cap] = kFar;
-        lds[2 * plane + cap] = kFar;
-    }
+    if (threadIdx.x == 0) lds[cap] = make_double4(kFar, kFar, kFar, 0.0);
     __syncthreads();
 }
 
@@ -637,7 +631,7 @@ __device__ __forceinline__ void scan_tiles(const Sys& s) {
 
 __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
-    extern __shared__ double lds[];
+    extern __shared__ double4 lds4[];
     __shared__ int red[kBlock / kWave];
     constexpr int TPP = kTileTpp;
     const int tile = bid;
@@ -651,14 +645,13 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     const int row0 = nseg >= 0 ? s.tile_row0[tile] : 0;
     const int4* seg = s.tile_seg + (size_t)tile * kSegMax;
     const int cap = s.lds_cap;
-    const int plane = lds_plane(cap);
     if (nseg >= 0) {
         const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
         const int nchk = s.tile_nchunk[tile];
         RegionBatch rb;
         region_issue(s, s.tpos, tile, nchk, wv, rb);
-        region_store(s, lds, plane, rb);
-        region_finish(s, s.tpos, lds, cap, tile, nchk, wv, rb);
+        region_store(s, lds4, rb);
+        region_finish(s, s.tpos, lds4, cap, tile, nchk, wv, rb);
     }
     const double4 xi = s.tpos[ii];
     if (act && q == 0) {
@@ -726,8 +719,8 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                     if (cand) {
                         if (nseg >= 0) {
                             int m = max(base, 0) + (j - cb);
-                            double ex = lds[m] - xi.x, ey = lds[plane + m] - xi.y,
-                                   ez = lds[2 * plane + m] - xi.z;
+                            const double2 pxy = *reinterpret_cast<const double2*>(&lds4[m]);
+                            double ex = pxy.x - xi.x, ey = pxy.y - xi.y, ez = lds4[m].z - xi.z;
                             r2 = ex * ex + ey * ey + ez * ez;
                             ent = m | code << kSlotBits;
                         } else {
@@ -991,12 +984,13 @@ constexpr int kPrefetch = MD_VERTEX_PREFETCH;  // list entries held in registers
 // image.  The cut-off selects a 0/1 factor, so every lane runs the same
 // instruction stream.
 template <int PREC, bool ENERGY>
-__device__ __forceinline__ void lj_lds_term(const Sys& s, const double* lds, int plane, int k,
+__device__ __forceinline__ void lj_lds_term(const Sys& s, const double4* lds, int k,
                                             const double4& xi, Acc3<PREC>& f, double& e,
                                             double& w) {
-    double dx = lds[k] - xi.x;
-    double dy = lds[plane + k] - xi.y;
-    double dz = lds[2 * plane + k] - xi.z;
+    const double2 pxy = *reinterpret_cast<const double2*>(&lds[k]);
+    double dx = pxy.x - xi.x;
+    double dy = pxy.y - xi.y;
+    double dz = lds[k].z - xi.z;
     double r2 = dx * dx + dy * dy + dz * dz;
     bool in = r2 < s.rc2;
     if (PREC == 0) {
@@ -1033,7 +1027,7 @@ template <int PREC, int TPP, bool KICK, bool ENERGY>
 __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     static_assert(TPP * kTile == kBlock, "one tile per workgroup");
     static_assert(kPrefetch % 4 == 0, "groups of four");
-    extern __shared__ double lds[];
+    extern __shared__ double4 lds4[];
     const int tile = bid;
     const int i = tile * kTile + threadIdx.x / TPP;
     const int q = threadIdx.x % TPP;
@@ -1048,7 +1042,6 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     double e = 0, w = 0;
     if (nseg >= 0) {
         constexpr int E = kPrefetch;
-        const int plane = lds_plane(cap);
         const int* nb = list_row(s, ii);
         int mine = cnt > q ? (cnt - q + TPP - 1) / TPP : 0;  // entries of this lane
         int mmax = mine;
@@ -1077,14 +1070,14 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
                 if (m0 + m < mmax) {
 #pragma unroll
                     for (int u = 0; u < 4; u++)
-                        lj_lds_term<PREC, ENERGY>(s, lds, plane, en[m + u], xi, f, e, w);
+                        lj_lds_term<PREC, ENERGY>(s, lds4, en[m + u], xi, f, e, w);
                 }
             }
         };
         int ea[E], eb[E];
         load_block(0, ea);
-        region_store(s, lds, plane, rb);
-        region_finish(s, s.pos, lds, cap, tile, nchk, wv, rb);
+        region_store(s, lds4, rb);
+        region_finish(s, s.pos, lds4, cap, tile, nchk, wv, rb);
         // long lists: blocks of E entries, the next block's loads in flight
         // while the current one is evaluated
         for (int m0 = 0; m0 < mmax; m0 += 2 * E) {
@@ -1761,17 +1754,17 @@ hipError_t launch_clear_ctrl(const Sys& s, hipStream_t st) {
 }
 
 hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) {
-    // cells: bin (+ scan by the last workgroup), scatter + tile regions, sort +
-    // reorder; lists: build (+ half-list scan by the last workgroup), half fill
+    // cells: bin (+ scan by the last workgroup), scatter, sort + reorder beside
+    // the tile regions; lists: build (+ half-list scan by the last workgroup),
+    // half fill
     if (cells) {
         hipLaunchKernelGGL(k_cell_bin, grid_n(s.n), dim3(kBlock), 0, st, s);
-        hipLaunchKernelGGL(k_scatter_tiles, dim3((unsigned)class_blocks(s, kClsScatter)),
-                           dim3(kBlock), 0, st, s);
-        hipLaunchKernelGGL(k_cell_sort, dim3((unsigned)(((long long)s.ncell * kWave + kBlock - 1) / kBlock)),
+        hipLaunchKernelGGL(k_cell_scatter, grid_n(s.n), dim3(kBlock), 0, st, s);
+        hipLaunchKernelGGL(k_sort_tiles, dim3((unsigned)class_blocks(s, kClsSortTiles)),
                            dim3(kBlock), 0, st, s);
     }
     if (lists) {
-        size_t sh_pos = 3 * sizeof(double) * (size_t)(s.lds_cap + 8);
+        size_t sh_pos = lds_region_bytes(s.lds_cap);
         size_t sh_map = sizeof(int) * (size_t)(s.lds_cap + 8);
         hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), sh_pos, st, s);
         hipLaunchKernelGGL(k_half_fill, dim3(s.ntiles), dim3(kBlock), sh_map, st, s);
@@ -1800,7 +1793,7 @@ static void vertex_dispatch(const Sys& s, bool kick, bool energy, hipStream_t st
     if (s.pot == 0) {
         constexpr int T = kTileTpp;
         dim3 gl((unsigned)s.ntiles);
-        size_t sh = 3 * sizeof(double) * (size_t)(s.lds_cap + 8);
+        size_t sh = lds_region_bytes(s.lds_cap);
         if (kick)
             hipLaunchKernelGGL((k_vertex_lj<PREC, T, true, false>), gl, b, sh, st, s);
         else if (energy)
@@ -1821,7 +1814,7 @@ template <int PREC>
 static void edge_dispatch(const Sys& s, int grid, hipStream_t st) {
     dim3 g(grid), b(kBlock);
     if (s.pot == 0) {
-        size_t sh = 3 * sizeof(double) * (size_t)lds_plane(s.lds_cap);
+        size_t sh = lds_acc_bytes(s.lds_cap);
         hipLaunchKernelGGL((k_edge_lj_tile<PREC>), dim3((unsigned)s.ntiles), b, sh, st, s);
     } else {
         hipLaunchKernelGGL((k_edge<1, PREC>), g, b, 0, st, s);
@@ -1834,7 +1827,7 @@ static void newton_dispatch(const Sys& s, hipStream_t st) {
     if (s.nrep > 0) {
         hipLaunchKernelGGL((k_newton_lj<PREC, true>), g, b, 0, st, s);
     } else {
-        size_t sh = 3 * sizeof(double) * (size_t)lds_plane(s.lds_cap);
+        size_t sh = lds_acc_bytes(s.lds_cap);
         hipLaunchKernelGGL((k_newton_lj<PREC, false>), g, b, sh, st, s);
     }
 }
@@ -1933,15 +1926,13 @@ __global__ __launch_bounds__(kBlock) void kb_cell_bin(BatchDev b, int step) {
     batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_cell_bin(s, lb, s.nblk); });
 }
 
-__global__ __launch_bounds__(kBlock) void kb_scatter_tiles(BatchDev b, int step) {
-    batch_block<kClsScatter>(b, step, [](const Sys& s, int lb) {
-        b_scatter_tiles(s, lb, class_blocks(s, kClsScatter));
-    });
+__global__ __launch_bounds__(kBlock) void kb_cell_scatter(BatchDev b, int step) {
+    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_cell_scatter(s, lb, s.nblk); });
 }
 
-__global__ __launch_bounds__(kBlock) void kb_cell_sort(BatchDev b, int step) {
-    batch_block<kClsCellSort>(b, step, [](const Sys& s, int lb) {
-        b_cell_sort(s, lb, class_blocks(s, kClsCellSort));
+__global__ __launch_bounds__(kBlock) void kb_sort_tiles(BatchDev b, int step) {
+    batch_block<kClsSortTiles>(b, step, [](const Sys& s, int lb) {
+        b_sort_tiles(s, lb, class_blocks(s, kClsSortTiles));
     });
 }
 
@@ -1997,7 +1988,9 @@ __global__ __launch_bounds__(kBlock) void kb_advance(BatchDev b, int steps) {
 
 hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int lds_cap, int mode,
                               int steps, hipStream_t st) {
-    const size_t sh_pos = 3 * sizeof(double) * (size_t)(lds_cap + 8);
+    // region staging needs the larger of the two LDS layouts
+    const size_t sh_pos = lds_region_bytes(lds_cap) > lds_acc_bytes(lds_cap) ? lds_region_bytes(lds_cap)
+                                                                            : lds_acc_bytes(lds_cap);
     const size_t sh_map = sizeof(int) * (size_t)(lds_cap + 8);
     auto g = [&](int cls) { return dim3((unsigned)grid[cls]); };
     const dim3 blk(kBlock);
@@ -2005,8 +1998,8 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int lds_cap, i
         if (mode == 0) hipLaunchKernelGGL(kb_kick_drift<false>, g(kClsParticle), blk, 0, st, b, k);
         else hipLaunchKernelGGL(kb_kick_drift<true>, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_cell_bin, g(kClsParticle), blk, 0, st, b, k);
-        hipLaunchKernelGGL(kb_scatter_tiles, g(kClsScatter), blk, 0, st, b, k);
-        hipLaunchKernelGGL(kb_cell_sort, g(kClsCellSort), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_cell_scatter, g(kClsParticle), blk, 0, st, b, k);
+        hipLaunchKernelGGL(kb_sort_tiles, g(kClsSortTiles), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_build, g(kClsTile), blk, sh_pos, st, b, k);
         hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
         if (mode == 0) {
