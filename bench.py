@@ -317,6 +317,13 @@ def main():
                      "bytes_per_launch": nb, "avg_launch_us": t_kernel * 1e6},
         "modes": modes,
     }
+    # HBM traffic of the same kernel from the committed FETCH_SIZE / WRITE_SIZE
+    # record, used only while the kernel sources are the ones it was taken on
+    from paper_1401_4350_amd import prof
+    rec = prof.read_record(os.path.join(ROOT, "profiles", f"traffic_{w.name}_{args.prec}.txt"))
+    if rec and rec.get("source_sha") == prof.source_hash():
+        out["roofline"]["traffic"] = float(rec["traffic_bytes"])
+        out["roofline"]["traffic_over_algorithmic"] = float(rec["traffic_bytes"]) / nb
     if args.serving_requests > 0:
         out["serving"] = serving_bench(args.serving_requests, args.serving_rate,
                                        args.serving_steps)

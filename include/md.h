@@ -216,12 +216,15 @@ void md_destroy(md_system* s);
  * differs only by the order of its atomic additions.
  *
  * The batch keeps a device table of per-slot descriptors and, per block class
- * of the step, a map from grid block to (slot, block of that system).  Grids
+ * of the step, a map from grid block to (slot, block of that system).  Maps
  * are sized once from max_systems and max_particles, so admission and
- * retirement only rewrite the table and maps between launches.  A launch
- * runs steps_per_launch steps (fewer when no system needs that many) as one
- * hipGraph, captured on first use and again only when an admitted system
- * needs a larger LDS region than the captured graph provides.
+ * retirement only rewrite the table and maps between launches.  The kernels
+ * that hold a tile's neighbour region in LDS run in three LDS-size buckets,
+ * each launched with its own LDS, so that systems with large regions do not
+ * lower the occupancy of the others.  A launch runs steps_per_launch steps
+ * (fewer when no system needs that many) as one hipGraph; grids are the
+ * blocks in use rounded up to a power of two, and a graph is captured the
+ * first time a combination of grids occurs (a few dozen are kept).
  * ------------------------------------------------------------------------- */
 typedef struct md_batch md_batch; /* opaque handle */
 
@@ -275,7 +278,7 @@ md_status md_batch_sync(md_batch* b);
 
 typedef struct {
     int32_t active;          /* admitted systems                                     */
-    int32_t lds_cap;         /* LDS region capacity of the captured graph (slots)    */
+    int32_t lds_cap;         /* region capacity (slots) of the largest LDS bucket in use */
     int64_t particles;       /* sum of n over admitted systems                       */
     uint64_t bytes;          /* sum of their footprints                              */
     int64_t launches;        /* md_batch_step launches so far                        */

@@ -681,8 +681,11 @@ BatchLayout batch_layout(const md_batch_params& p) {
     c[md::kClsTile] = tiles;
     // cell sort: at most nblk blocks per system; tile regions: 4 tiles per block
     c[md::kClsSortTiles] = c[md::kClsParticle] + (tiles + 3) / 4 + smax;
-    c[md::kClsVertex] = tiles;
-    c[md::kClsEdge] = 4 * tiles;
+    for (int b = 0; b < md::kLdsBuckets; b++) {
+        c[md::kClsBuild0 + b] = tiles;
+        c[md::kClsVertex0 + b] = tiles;
+        c[md::kClsEdge0 + b] = 4 * tiles;
+    }
     uint64_t cur = 0;
     L.tab = take(cur, sizeof(md::Sys) * (uint64_t)smax);
     L.left = take(cur, 4 * (uint64_t)smax);
@@ -723,7 +726,6 @@ struct md_batch {
     int active = 0;
     long long particles = 0;
     uint64_t bytes = 0;
-    int lds_cap = 512;  // LDS region capacity the graphs are captured for
     // Captured launches, keyed by steps and the grid of every class.  Grids
     // are the blocks in use rounded up to a power of two, so admissions and
     // retirements reuse a captured graph until a class crosses a power of two.
@@ -752,9 +754,15 @@ struct md_batch {
         graphs.clear();
     }
     // Grid of every class for the current admissions: the blocks in use,
-    // rounded up to a power of two for captured graphs.
+    // rounded up to a power of two for captured graphs; 0 for a bucket class
+    // no admitted system uses (not launched).
     void grids(bool bucket, int* out) const {
         for (int c = 0; c < md::kNumClasses; c++) {
+            bool bucketed = c >= md::kClsBuild0;
+            if (bucketed && used[c] == 0) {
+                out[c] = 0;
+                continue;
+            }
             int u = std::max(used[c], 1);
             if (bucket) {
                 int g = 1;
@@ -824,7 +832,7 @@ struct md_batch {
         hipGraph_t graph = nullptr;
         md_status r = hip(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal), "begin capture");
         if (r != MD_OK) return r;
-        hipError_t e = md::launch_batch_steps(dev, grid, lds_cap, p.mode, steps, capture);
+        hipError_t e = md::launch_batch_steps(dev, grid, p.mode, steps, capture);
         hipError_t e2 = hipStreamEndCapture(capture, &graph);
         r = hip(e != hipSuccess ? e : e2, "capture batch step");
         hipGraphExec_t exec = nullptr;
@@ -923,10 +931,6 @@ md_status md_batch_admit(md_batch* b, md_system* s, int64_t nsteps, int32_t* slo
     b->active++;
     b->particles += s->p.n;
     b->bytes += foot;
-    if (s->sys.lds_cap > b->lds_cap) {  // graphs were captured with too little LDS
-        b->lds_cap = (s->sys.lds_cap + 511) / 512 * 512;
-        b->drop_graphs();
-    }
     s->batch = b;
     s->batch_slot = k;
     r = b->upload();
@@ -956,7 +960,7 @@ md_status md_batch_step(md_batch* b, int32_t* steps_run) {
         r = b->graph_for(steps, grid, &exec);
         if (r == MD_OK) r = b->hip(hipGraphLaunch(exec, b->stream), "graph launch");
     } else {
-        r = b->hip(md::launch_batch_steps(b->dev, grid, b->lds_cap, b->p.mode, steps, b->stream),
+        r = b->hip(md::launch_batch_steps(b->dev, grid, b->p.mode, steps, b->stream),
                    "batch launch");
     }
     if (r != MD_OK) return r;
@@ -1003,7 +1007,10 @@ md_status md_batch_sync(md_batch* b) {
 md_status md_batch_info(const md_batch* b, md_batch_info_t* out) {
     if (!b || !out) return MD_ERR_INVALID_ARG;
     out->active = b->active;
-    out->lds_cap = b->lds_cap;
+    int cap = 0;  // largest LDS bucket in use
+    for (int bk = 0; bk < md::kLdsBuckets; bk++)
+        if (b->used[md::kClsBuild0 + bk] > 0) cap = md::bucket_cap(bk);
+    out->lds_cap = cap;
     out->particles = b->particles;
     out->bytes = b->bytes;
     out->launches = b->launches;

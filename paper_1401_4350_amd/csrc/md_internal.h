@@ -133,10 +133,35 @@ enum BatchClass {
     kClsParticle = 0,  // nblk = ceil(n / kBlock)
     kClsTile,          // ntiles (one block per tile of kTile slots)
     kClsSortTiles,     // sort_blocks + ceil(ntiles / 4): cell sort, then a wavefront per tile
-    kClsVertex,        // LJ: ntiles, patchy: nblk
-    kClsEdge,          // LJ: ntiles, patchy: eblk
+    // Kernels that stage or accumulate over a tile's region in LDS come in
+    // three LDS buckets, each launched with its own fixed dynamic LDS, so a
+    // few small-box systems with large regions do not lower the occupancy of
+    // all the others.  A system's blocks go to the bucket of its region
+    // capacity (lds_bucket); its count in the other two is zero.
+    kClsBuild0,        // list build: ntiles
+    kClsBuild1,
+    kClsBuild2,
+    kClsVertex0,       // vertex pass: LJ ntiles, patchy nblk
+    kClsVertex1,
+    kClsVertex2,
+    kClsEdge0,         // edge pass: LJ ntiles, patchy eblk
+    kClsEdge1,
+    kClsEdge2,
     kNumClasses
 };
+
+constexpr int kLdsBuckets = 3;
+
+// Largest region capacity (slots) of each LDS bucket: with 32-byte records,
+// bucket 0 leaves room for three workgroups per CU, bucket 1 for two.
+__host__ __device__ inline int bucket_cap(int b) {
+    return b == 0 ? 1664 : (b == 1 ? 2432 : kLdsCapMax);
+}
+
+__host__ __device__ inline int lds_bucket(const Sys& s) {
+    if (s.pot != 0) return 0;  // the patchy passes use no region
+    return s.lds_cap <= bucket_cap(0) ? 0 : (s.lds_cap <= bucket_cap(1) ? 1 : 2);
+}
 
 struct BatchDev {
     const Sys* tab;   // [max_systems] descriptors, indexed by slot
@@ -158,17 +183,21 @@ __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
         case kClsParticle: return s.nblk;
         case kClsTile: return s.ntiles;
         case kClsSortTiles: return sort_blocks(s) + (s.ntiles + kBlock / kWave - 1) / (kBlock / kWave);
-        case kClsVertex: return s.pot == 0 ? s.ntiles : s.nblk;
-        default: return s.pot == 0 ? s.ntiles : s.eblk;  // LJ edge: one block per tile
+        case kClsBuild0: case kClsBuild1: case kClsBuild2:
+            return lds_bucket(s) == cls - kClsBuild0 ? s.ntiles : 0;
+        case kClsVertex0: case kClsVertex1: case kClsVertex2:
+            return lds_bucket(s) == cls - kClsVertex0 ? (s.pot == 0 ? s.ntiles : s.nblk) : 0;
+        default:
+            return lds_bucket(s) == cls - kClsEdge0 ? (s.pot == 0 ? s.ntiles : s.eblk) : 0;
     }
 }
 
 // Enqueues `steps` batched steps (forces by `mode`) plus the step-count
 // update on `st`; the kernels of class c get grid[c] blocks (at most the map
-// capacity of the class, at least the blocks in use), dynamic LDS for regions
-// of lds_cap slots.
-hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int lds_cap, int mode,
-                              int steps, hipStream_t st);
+// capacity of the class, at least the blocks in use; a class with no blocks
+// is not launched).
+hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int steps,
+                              hipStream_t st);
 
 // Host-side launchers (md_kernels.hip).  All enqueue on `st`.
 hipError_t launch_set_rebuild(const Sys& s, hipStream_t st);

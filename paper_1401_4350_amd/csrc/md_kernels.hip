@@ -1936,8 +1936,9 @@ __global__ __launch_bounds__(kBlock) void kb_sort_tiles(BatchDev b, int step) {
     });
 }
 
+template <int C>
 __global__ __launch_bounds__(kBlock) void kb_build(BatchDev b, int step) {
-    batch_block<kClsTile>(b, step, [](const Sys& s, int lb) { b_build(s, lb, s.ntiles); });
+    batch_block<C>(b, step, [](const Sys& s, int lb) { b_build(s, lb, s.ntiles); });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_half_fill(BatchDev b, int step) {
@@ -1946,8 +1947,9 @@ __global__ __launch_bounds__(kBlock) void kb_half_fill(BatchDev b, int step) {
 
 // Vertex forces with the closing half kick, dispatched per block on the
 // system's potential and precision (uniform branches).
+template <int C>
 __global__ __launch_bounds__(kBlock) void kb_vertex(BatchDev b, int step) {
-    batch_block<kClsVertex>(b, step, [](const Sys& s, int lb) {
+    batch_block<C>(b, step, [](const Sys& s, int lb) {
         constexpr int T = kTileTpp;
         if (s.pot == 0) {
             if (s.prec == 0) b_vertex_lj<0, T, true, false>(s, lb, s.ntiles);
@@ -1961,8 +1963,9 @@ __global__ __launch_bounds__(kBlock) void kb_vertex(BatchDev b, int step) {
     });
 }
 
+template <int C>
 __global__ __launch_bounds__(kBlock) void kb_edge(BatchDev b, int step) {
-    batch_block<kClsEdge>(b, step, [](const Sys& s, int lb) {
+    batch_block<C>(b, step, [](const Sys& s, int lb) {
         if (s.pot == 0) {
             if (s.prec == 0) b_edge_lj_tile<0>(s, lb, s.ntiles);
             else b_edge_lj_tile<1>(s, lb, s.ntiles);
@@ -1986,26 +1989,44 @@ __global__ __launch_bounds__(kBlock) void kb_advance(BatchDev b, int steps) {
     if (i < b.nslots) b.left[i] = max(0, b.left[i] - steps);
 }
 
-hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int lds_cap, int mode,
-                              int steps, hipStream_t st) {
-    // region staging needs the larger of the two LDS layouts
-    const size_t sh_pos = lds_region_bytes(lds_cap) > lds_acc_bytes(lds_cap) ? lds_region_bytes(lds_cap)
-                                                                            : lds_acc_bytes(lds_cap);
-    const size_t sh_map = sizeof(int) * (size_t)(lds_cap + 8);
-    auto g = [&](int cls) { return dim3((unsigned)grid[cls]); };
+hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int steps,
+                              hipStream_t st) {
     const dim3 blk(kBlock);
+    auto g = [&](int cls) { return dim3((unsigned)grid[cls]); };
+    // one launch per LDS bucket in use, each with that bucket's LDS
+    auto per_bucket = [&](auto launch) {
+        launch(std::integral_constant<int, 0>{});
+        launch(std::integral_constant<int, 1>{});
+        launch(std::integral_constant<int, 2>{});
+    };
+    const size_t sh_map = sizeof(int) * (size_t)(kLdsCapMax + 8);
     for (int k = 0; k < steps; k++) {
         if (mode == 0) hipLaunchKernelGGL(kb_kick_drift<false>, g(kClsParticle), blk, 0, st, b, k);
         else hipLaunchKernelGGL(kb_kick_drift<true>, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_cell_bin, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_cell_scatter, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_sort_tiles, g(kClsSortTiles), blk, 0, st, b, k);
-        hipLaunchKernelGGL(kb_build, g(kClsTile), blk, sh_pos, st, b, k);
+        per_bucket([&](auto bk) {
+            constexpr int B = decltype(bk)::value;
+            if (grid[kClsBuild0 + B] > 0)
+                hipLaunchKernelGGL(kb_build<kClsBuild0 + B>, g(kClsBuild0 + B), blk,
+                                   lds_region_bytes(bucket_cap(B)), st, b, k);
+        });
         hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
         if (mode == 0) {
-            hipLaunchKernelGGL(kb_vertex, g(kClsVertex), blk, sh_pos, st, b, k);
+            per_bucket([&](auto bk) {
+                constexpr int B = decltype(bk)::value;
+                if (grid[kClsVertex0 + B] > 0)
+                    hipLaunchKernelGGL(kb_vertex<kClsVertex0 + B>, g(kClsVertex0 + B), blk,
+                                       lds_region_bytes(bucket_cap(B)), st, b, k);
+            });
         } else {
-            hipLaunchKernelGGL(kb_edge, g(kClsEdge), blk, sh_pos, st, b, k);
+            per_bucket([&](auto bk) {
+                constexpr int B = decltype(bk)::value;
+                if (grid[kClsEdge0 + B] > 0)
+                    hipLaunchKernelGGL(kb_edge<kClsEdge0 + B>, g(kClsEdge0 + B), blk,
+                                       lds_acc_bytes(bucket_cap(B)), st, b, k);
+            });
             hipLaunchKernelGGL(kb_kick, g(kClsParticle), blk, 0, st, b, k);
         }
     }
