@@ -594,7 +594,8 @@ md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pai
     if (!s || !n_pairs || cap < 0 || (cap > 0 && !pairs)) return MD_ERR_INVALID_ARG;
     if (s->batch) return s->admitted();
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
-    md_status r = s->sync_check();
+    md_status r = s->hip(md::launch_half_fill(s->sys, s->stream), "half list");
+    if (r == MD_OK) r = s->sync_check();
     if (r != MD_OK) return r;
     md::Ctrl c;
     r = s->hip(hipMemcpy(&c, s->sys.ctrl, sizeof c, hipMemcpyDeviceToHost), "ctrl");

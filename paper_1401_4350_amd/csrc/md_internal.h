@@ -34,8 +34,10 @@ struct Ctrl {
     long long npairs;   // half-list entries at the last build (clamped to capacity)
     long long rebuilds; // number of builds
     int done_build;     // workgroups of the list build that have finished
+    int half_stale;     // the half list predates the last build (filled on demand)
+    int done_half;      // workgroups of the half-list fill that have finished
     int pad1;
-    long long pad[3];
+    long long pad[2];
 };
 
 // Pair-potential constants in the arithmetic type of the pair maths.
@@ -203,6 +205,9 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
 hipError_t launch_set_rebuild(const Sys& s, hipStream_t st);
 hipError_t launch_clear_ctrl(const Sys& s, hipStream_t st);
 hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists);
+// Fills the half list if the last build made it stale (returns at once
+// otherwise); the edge and Newton passes and the pair download need it.
+hipError_t launch_half_fill(const Sys& s, hipStream_t st);
 hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_t st,
                          int edge_grid);
 hipError_t launch_kick_drift(const Sys& s, bool zero_forces, hipStream_t st);

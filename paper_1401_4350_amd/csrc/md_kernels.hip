@@ -252,6 +252,8 @@ __global__ void k_clear_ctrl(Ctrl* c) {
     c->npairs = 0;
     c->rebuilds = 0;
     c->done_build = 0;
+    c->half_stale = 0;
+    c->done_half = 0;
 }
 
 // True in the one workgroup, of the nb that call this with the same counter,
@@ -626,6 +628,7 @@ __device__ __forceinline__ void scan_tiles(const Sys& s) {
         s.ctrl->npairs = tot < cap ? tot : cap;
         if (tot > cap) atomicOr(&s.ctrl->overflow, 1);
         s.ctrl->rebuilds += 1;
+        s.ctrl->half_stale = 1;
     }
 }
 
@@ -780,14 +783,15 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
 __global__ __launch_bounds__(kBlock) void k_build(Sys s) { b_build(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
 
 
-// Half list (edge pass): one workgroup per tile, four lanes per particle.
+// Half list (edge and Newton passes), filled on demand after a build: one
+// workgroup per tile, four lanes per particle.
 // Row starts are the tile offset plus a prefix over the tile's particles; a
 // staged tile first maps its LDS indices back to slots (in LDS); each
 // particle's lanes walk its full list and keep the entries with j > i,
 // compacted with a ballot (list order is kept).  Records the chunk heads
 // (first row of every 64-entry chunk) that the edge pass uses.
 __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
-    if (!s.ctrl->rebuild) return;
+    if (!s.ctrl->half_stale) return;
     extern __shared__ int map[];
     __shared__ int hpre[kTile];
     constexpr int TPP = kTileTpp;
@@ -853,6 +857,9 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
         }
         k += __builtin_popcount(grp);
     }
+    // the last workgroup marks the list current (every workgroup has passed
+    // its check of the flag by then)
+    if (last_block(&s.ctrl->done_half, nb) && threadIdx.x == 0) s.ctrl->half_stale = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_half_fill(Sys s) { b_half_fill(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
@@ -1755,8 +1762,8 @@ hipError_t launch_clear_ctrl(const Sys& s, hipStream_t st) {
 
 hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) {
     // cells: bin (+ scan by the last workgroup), scatter, sort + reorder beside
-    // the tile regions; lists: build (+ half-list scan by the last workgroup),
-    // half fill
+    // the tile regions; lists: build (+ half-list offsets by the last
+    // workgroup); the half list itself is filled on demand (launch_half_fill)
     if (cells) {
         hipLaunchKernelGGL(k_cell_bin, grid_n(s.n), dim3(kBlock), 0, st, s);
         hipLaunchKernelGGL(k_cell_scatter, grid_n(s.n), dim3(kBlock), 0, st, s);
@@ -1765,10 +1772,14 @@ hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) 
     }
     if (lists) {
         size_t sh_pos = lds_region_bytes(s.lds_cap);
-        size_t sh_map = sizeof(int) * (size_t)(s.lds_cap + 8);
         hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), sh_pos, st, s);
-        hipLaunchKernelGGL(k_half_fill, dim3(s.ntiles), dim3(kBlock), sh_map, st, s);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_half_fill(const Sys& s, hipStream_t st) {
+    size_t sh_map = sizeof(int) * (size_t)(s.lds_cap + 8);
+    hipLaunchKernelGGL(k_half_fill, dim3(s.ntiles), dim3(kBlock), sh_map, st, s);
     return hipGetLastError();
 }
 
@@ -1838,6 +1849,7 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
         else if (prec == 1) vertex_dispatch<1>(s, kick, false, st);
         else vertex_dispatch<2>(s, kick, false, st);
     } else if (mode == 2) {  // Newton (LJ); with atomics into F it must start at zero
+        launch_half_fill(s, st);
         if (s.nrep == 0 && !kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) newton_dispatch<0>(s, st);
         else newton_dispatch<1>(s, st);  // FP32 pair maths, FP64 sums
@@ -1849,6 +1861,7 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
         }
         if (!kick) hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
     } else {
+        launch_half_fill(s, st);
         if (!kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) edge_dispatch<0>(s, edge_grid, st);
         else edge_dispatch<1>(s, edge_grid, st);  // FP32 pair maths, FP64 atomics
@@ -2012,7 +2025,6 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
                 hipLaunchKernelGGL(kb_build<kClsBuild0 + B>, g(kClsBuild0 + B), blk,
                                    lds_region_bytes(bucket_cap(B)), st, b, k);
         });
-        hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
         if (mode == 0) {
             per_bucket([&](auto bk) {
                 constexpr int B = decltype(bk)::value;
@@ -2021,6 +2033,7 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
                                        lds_region_bytes(bucket_cap(B)), st, b, k);
             });
         } else {
+            hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
             per_bucket([&](auto bk) {
                 constexpr int B = decltype(bk)::value;
                 if (grid[kClsEdge0 + B] > 0)
