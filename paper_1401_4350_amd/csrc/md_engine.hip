@@ -28,7 +28,7 @@ struct Layout {
     // state offsets
     uint64_t pos, vel, frc, quat, angm, trq, id;
     // workspace offsets
-    uint64_t xbuild, tpos, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
+    uint64_t pos_alt, xbuild, tpos, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
         ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, epart, wpart, kpart, red, ctrl, tile_seg,
         tile_nseg, tile_chunk, tile_nchunk, tile_row0;
     int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
@@ -108,6 +108,7 @@ Layout layout(const md_params& p) {
     L.state_bytes = cur;
     cur = 0;
     L.ctrl = take(cur, sizeof(md::Ctrl));
+    L.pos_alt = take(cur, d4);
     L.xbuild = take(cur, d4);
     L.tpos = take(cur, d4);
     L.tvel = take(cur, d4);
@@ -282,6 +283,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.trq = patchy ? (double4*)(S + L.trq) : nullptr;
     y.id = (int*)(S + L.id);
     y.ctrl = (md::Ctrl*)(W + L.ctrl);
+    y.pos_alt = (double4*)(W + L.pos_alt);
     y.xbuild = (double4*)(W + L.xbuild);
     y.tpos = (double4*)(W + L.tpos);
     y.tvel = (double4*)(W + L.tvel);
@@ -449,7 +451,12 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
         md_status r = md_forces(s, mode);
         if (r != MD_OK) return r;
     }
-    const md::Sys& y = s->sys;
+    // The vertex LJ pass also does the next step's half kick and drift (into
+    // the second position buffer, whose role swaps with the first every
+    // fused step), so after the first step one MD step is the rebuild test
+    // chain and one force launch.
+    md::Sys y = s->sys;
+    const bool fuse = mode == MD_MODE_VERTEX && s->p.pot == MD_POT_LJ;
     // passes that add with atomics into the force array need it cleared first
     bool edge = mode == MD_MODE_EDGE || (mode == MD_MODE_NEWTON && s->sys.nrep == 0);
     bool prof = s->profiling;
@@ -461,14 +468,23 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     for (int k = 0; k < nsteps; k++) {
         hipEvent_t* ev = prof ? &s->events[4 * (size_t)k] : nullptr;
         hipError_t e = prof ? hipEventRecord(ev[0], st) : hipSuccess;
-        if (e == hipSuccess) e = md::launch_kick_drift(y, edge, st);
+        if (e == hipSuccess && (!fuse || k == 0)) e = md::launch_kick_drift(y, edge, st);
         if (e == hipSuccess && prof) e = hipEventRecord(ev[1], st);
         if (e == hipSuccess) e = md::launch_rebuild(y, st, true, true);
         if (e == hipSuccess && prof) e = hipEventRecord(ev[2], st);
-        if (e == hipSuccess) e = md::launch_forces(y, mode, s->p.prec, true, st, s->edge_grid);
+        if (fuse && k + 1 < nsteps) {
+            if (e == hipSuccess) e = md::launch_vertex_kick_drift(y, s->p.prec, st);
+            std::swap(y.pos, y.pos_alt);
+        } else if (e == hipSuccess) {
+            e = md::launch_forces(y, mode, s->p.prec, true, st, s->edge_grid);
+        }
         if (e == hipSuccess && prof) e = hipEventRecord(ev[3], st);
-        if (e != hipSuccess) return s->hip(e, "step launch");
+        if (e != hipSuccess) {
+            s->sys = y;
+            return s->hip(e, "step launch");
+        }
     }
+    s->sys = y;
     s->steps += nsteps;
     md_status r = s->sync_check();
     if (r != MD_OK || !prof) return r;

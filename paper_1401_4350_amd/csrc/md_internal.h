@@ -83,6 +83,7 @@ struct Sys {
     int* id;         // slot -> original id
 
     // workspace
+    double4* pos_alt;  // second position buffer (vertex pass with the next drift)
     double4* xbuild;
     double4* tpos;
     double4* tvel;
@@ -211,6 +212,9 @@ hipError_t launch_half_fill(const Sys& s, hipStream_t st);
 hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_t st,
                          int edge_grid);
 hipError_t launch_kick_drift(const Sys& s, bool zero_forces, hipStream_t st);
+// LJ vertex forces with the closing half kick and the next step's half kick,
+// drift (into pos_alt) and rebuild test.
+hipError_t launch_vertex_kick_drift(const Sys& s, int prec, hipStream_t st);
 hipError_t launch_kick(const Sys& s, hipStream_t st);
 hipError_t launch_energy(const Sys& s, int prec, hipStream_t st);
 hipError_t launch_clear_rebuild(const Sys& s, hipStream_t st);

@@ -629,6 +629,7 @@ __device__ __forceinline__ void scan_tiles(const Sys& s) {
         if (tot > cap) atomicOr(&s.ctrl->overflow, 1);
         s.ctrl->rebuilds += 1;
         s.ctrl->half_stale = 1;
+        s.ctrl->rebuild = 0;  // every workgroup of the build has read it
     }
 }
 
@@ -1030,15 +1031,19 @@ __device__ __forceinline__ void lj_lds_term(const Sys& s, const double4* lds, in
 // into LDS meanwhile, then evaluates the entries from LDS in groups of four
 // under a wave-uniform trip count (entries past the list end point at the
 // padding slot).  Unstaged tiles gather from global memory.
-template <int PREC, int TPP, bool KICK, bool ENERGY>
+// DRIFT (with KICK): after the closing half kick, also the next step's half
+// kick and drift, written to the other position buffer (pos_alt) because the
+// neighbours still read pos, and the next step's rebuild test; the same
+// arithmetic as k_kick followed by k_kick_drift.
+template <int PREC, int TPP, bool KICK, bool ENERGY, bool DRIFT = false>
 __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     static_assert(TPP * kTile == kBlock, "one tile per workgroup");
     static_assert(kPrefetch % 4 == 0, "groups of four");
+    static_assert(!DRIFT || KICK, "the drift follows the closing kick");
     extern __shared__ double4 lds4[];
     const int tile = bid;
     const int i = tile * kTile + threadIdx.x / TPP;
     const int q = threadIdx.x % TPP;
-    if (KICK && bid == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
     const int nseg = s.tile_nseg[tile];
     const int cap = s.lds_cap;
     bool act = i < s.n;
@@ -1122,12 +1127,27 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
         v.x += s.hdt * fx * s.inv_mass;
         v.y += s.hdt * fy * s.inv_mass;
         v.z += s.hdt * fz * s.inv_mass;
+        if (DRIFT) {
+            v.x += s.hdt * fx * s.inv_mass;
+            v.y += s.hdt * fy * s.inv_mass;
+            v.z += s.hdt * fz * s.inv_mass;
+            double4 x = xi;
+            x.x += s.dt * v.x;  // unwrapped until the next list build
+            x.y += s.dt * v.y;
+            x.z += s.dt * v.z;
+            s.pos_alt[i] = x;
+            const double4 xb = s.xbuild[i];
+            const double ddx = x.x - xb.x, ddy = x.y - xb.y, ddz = x.z - xb.z;
+            if (ddx * ddx + ddy * ddy + ddz * ddz > s.disp2) s.ctrl->rebuild = 1;
+        }
         s.vel[i] = v;
     }
 }
 
-template <int PREC, int TPP, bool KICK, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) { b_vertex_lj<PREC, TPP, KICK, ENERGY>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+template <int PREC, int TPP, bool KICK, bool ENERGY, bool DRIFT = false>
+__global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) {
+    b_vertex_lj<PREC, TPP, KICK, ENERGY, DRIFT>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
 
 template <int PREC, bool KICK, bool ENERGY>
 __device__ __forceinline__ void b_vertex_patchy(const Sys& s, int bid, int nb) {
@@ -1799,13 +1819,16 @@ void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, do
 }
 
 template <int PREC>
-static void vertex_dispatch(const Sys& s, bool kick, bool energy, hipStream_t st) {
+static void vertex_dispatch(const Sys& s, bool kick, bool energy, hipStream_t st,
+                            bool drift = false) {
     dim3 g(s.nblk), b(kBlock);
     if (s.pot == 0) {
         constexpr int T = kTileTpp;
         dim3 gl((unsigned)s.ntiles);
         size_t sh = lds_region_bytes(s.lds_cap);
-        if (kick)
+        if (kick && drift)
+            hipLaunchKernelGGL((k_vertex_lj<PREC, T, true, false, true>), gl, b, sh, st, s);
+        else if (kick)
             hipLaunchKernelGGL((k_vertex_lj<PREC, T, true, false>), gl, b, sh, st, s);
         else if (energy)
             hipLaunchKernelGGL((k_vertex_lj<PREC, T, false, true>), gl, b, sh, st, s);
@@ -1872,6 +1895,14 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
             hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex_kick_drift(const Sys& s, int prec, hipStream_t st) {
+    if (s.pot != 0) return hipErrorInvalidValue;
+    if (prec == 0) vertex_dispatch<0>(s, true, false, st, true);
+    else if (prec == 1) vertex_dispatch<1>(s, true, false, st, true);
+    else vertex_dispatch<2>(s, true, false, st, true);
     return hipGetLastError();
 }
 
