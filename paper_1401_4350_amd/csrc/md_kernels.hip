@@ -635,7 +635,6 @@ __device__ __forceinline__ void scan_tiles(const Sys& s) {
 
 __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
-    extern __shared__ double4 lds4[];
     __shared__ int red[kBlock / kWave];
     constexpr int TPP = kTileTpp;
     const int tile = bid;
@@ -648,15 +647,6 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     const int nseg = s.tile_nseg[tile];
     const int row0 = nseg >= 0 ? s.tile_row0[tile] : 0;
     const int4* seg = s.tile_seg + (size_t)tile * kSegMax;
-    const int cap = s.lds_cap;
-    if (nseg >= 0) {
-        const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-        const int nchk = s.tile_nchunk[tile];
-        RegionBatch rb;
-        region_issue(s, s.tpos, tile, nchk, wv, rb);
-        region_store(s, lds4, rb);
-        region_finish(s, s.tpos, lds4, cap, tile, nchk, wv, rb);
-    }
     const double4 xi = s.tpos[ii];
     if (act && q == 0) {
         s.pos[i] = xi;
@@ -707,6 +697,9 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                 const int cb = act ? s.cstart[rowbase + xa] : 0;
                 const int ce = act ? s.cstart[rowbase + xb + 1] : 0;
                 const int code = wx | wy << 2 | wz << 4;
+                // the run's periodic image, added as the region copy adds it
+                const double shx = (double)(wx - 1) * s.box, shy = (double)(wy - 1) * s.box,
+                             shz = (double)(wz - 1) * s.box;
                 int base = -1;
                 if (nseg >= 0 && cb < ce) {
                     // the two fixed segment slots of (home row, dz, dy)
@@ -723,8 +716,9 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                     if (cand) {
                         if (nseg >= 0) {
                             int m = max(base, 0) + (j - cb);
-                            const double2 pxy = *reinterpret_cast<const double2*>(&lds4[m]);
-                            double ex = pxy.x - xi.x, ey = pxy.y - xi.y, ez = lds4[m].z - xi.z;
+                            const double4 pj = s.tpos[j];
+                            double ex = (pj.x + shx) - xi.x, ey = (pj.y + shy) - xi.y,
+                                   ez = (pj.z + shz) - xi.z;
                             r2 = ex * ex + ey * ey + ez * ez;
                             ent = m | code << kSlotBits;
                         } else {
@@ -1790,10 +1784,7 @@ hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) 
         hipLaunchKernelGGL(k_sort_tiles, dim3((unsigned)class_blocks(s, kClsSortTiles)),
                            dim3(kBlock), 0, st, s);
     }
-    if (lists) {
-        size_t sh_pos = lds_region_bytes(s.lds_cap);
-        hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), sh_pos, st, s);
-    }
+    if (lists) hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), 0, st, s);
     return hipGetLastError();
 }
 
@@ -2053,8 +2044,7 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
         per_bucket([&](auto bk) {
             constexpr int B = decltype(bk)::value;
             if (grid[kClsBuild0 + B] > 0)
-                hipLaunchKernelGGL(kb_build<kClsBuild0 + B>, g(kClsBuild0 + B), blk,
-                                   lds_region_bytes(bucket_cap(B)), st, b, k);
+                hipLaunchKernelGGL(kb_build<kClsBuild0 + B>, g(kClsBuild0 + B), blk, 0, st, b, k);
         });
         if (mode == 0) {
             per_bucket([&](auto bk) {
