@@ -26,6 +26,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# Algorithmic FP64 operations of one LJ list entry in the vertex pass (FMA = 2):
+# separation 3, r^2 5, 1/r^2 1, (sigma/r)^2 1, ^6 2, force factor 5, the three
+# force components accumulated 6.
+LJ_ENTRY_FLOPS = 23
 
 
 def vertex_step_bytes(n: int, pairs: int) -> int:
@@ -319,7 +324,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_vertex_lj<FP64, closing kick + next kick and drift>",
-                     "bytes_per_launch": nb, "avg_launch_us": t_kernel * 1e6},
+                     "bytes_per_launch": nb, "avg_launch_us": t_kernel * 1e6,
+                     # the same kernel against the FP64 vector rate: 2|E| list
+                     # entries of LJ_ENTRY_FLOPS each per launch
+                     "valu": {"achieved": 2 * pairs * LJ_ENTRY_FLOPS / t_kernel / 1e12,
+                              "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": 2 * pairs * LJ_ENTRY_FLOPS / t_kernel / 1e12
+                              / FP64_VECTOR_PEAK_TFLOPS}},
         "modes": modes,
     }
     # HBM traffic of the same kernel from the committed FETCH_SIZE / WRITE_SIZE

@@ -708,22 +708,20 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                     base = (hr == 0 || hr == 1) ? tile_lds_base(sg, 2, cb, code) : -1;
                     if (base < 0) atomicOr(&s.ctrl->overflow, 2);  // region misses a cell
                 }
-                for (int j0 = cb; j0 < ce; j0 += TPP) {
-                    const int j = j0 + q;
-                    bool cand = j < ce && j != i;
+                // candidate j with its record pj (loaded by the caller)
+                auto consider = [&](int j, const double4& pj) {
+                    const bool cand = j < ce && j != i;
                     double r2 = 1e300;
                     int ent = 0;
                     if (cand) {
                         if (nseg >= 0) {
                             int m = max(base, 0) + (j - cb);
-                            const double4 pj = s.tpos[j];
                             double ex = (pj.x + shx) - xi.x, ey = (pj.y + shy) - xi.y,
                                    ez = (pj.z + shz) - xi.z;
                             r2 = ex * ex + ey * ey + ez * ez;
                             ent = m | code << kSlotBits;
                         } else {
-                            double4 xj = s.tpos[j];
-                            double ex = xj.x - xi.x, ey = xj.y - xi.y, ez = xj.z - xi.z;
+                            double ex = pj.x - xi.x, ey = pj.y - xi.y, ez = pj.z - xi.z;
                             double ddx = wrap_delta(ex, s.box, s.inv_box);
                             double ddy = wrap_delta(ey, s.box, s.inv_box);
                             double ddz = wrap_delta(ez, s.box, s.inv_box);
@@ -752,6 +750,15 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                             }
                     }
                     count += nk;
+                };
+                // two candidates per lane per round, both loads issued first
+                // (unconditionally, clamped into the run) so that they overlap
+                for (int j0 = cb; j0 < ce; j0 += 2 * TPP) {
+                    const int ja = j0 + q, jb = ja + TPP;
+                    const double4 pa = s.tpos[min(ja, ce - 1)];
+                    const double4 pb = s.tpos[min(jb, ce - 1)];
+                    consider(ja, pa);
+                    consider(jb, pb);
                 }
             }
         }
