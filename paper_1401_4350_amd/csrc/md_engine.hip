@@ -120,7 +120,8 @@ Layout layout(const md_params& p) {
     L.ccount = take(cur, 4 * (uint64_t)L.ncell);
     L.cstart = take(cur, 4 * ((uint64_t)L.ncell + 1));
     L.order = take(cur, 4 * n);
-    L.nbr = take(cur, 4 * (uint64_t)L.ntiles * md::kTile * 4 * ((p.max_neighbors + 3) / 4));
+    L.nbr = take(cur, 4 * ((uint64_t)L.ntiles * ((p.max_neighbors + 3) / 4) + md::kListPadRows) *
+                          md::kTile * 4);
     L.ncount = take(cur, 4 * n);
     L.hcount = take(cur, 4 * n);
     L.hstart = take(cur, 4 * (n + 1));

@@ -21,6 +21,7 @@ constexpr int kTileTpp = kBlock / kTile;  // lanes per particle in the tiled pas
 constexpr int kSegMax = 36;
 constexpr int kChunkMax = 96;
 constexpr int kLdsCapMax = 4096;  // particles per tile region (3 doubles each)
+constexpr int kListPadRows = 32;  // spare list rows after the last tile (prefetch reads)
 
 // Device-resident control block (one per system).  Written by kernels, read by
 // the host only at syncing calls.

@@ -1065,16 +1065,24 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
         const int nchk = s.tile_nchunk[tile];
         RegionBatch rb;
         region_issue(s, s.pos, tile, nchk, wv, rb);
-        // every lane issues all E loads of a block (past its list end it
-        // re-reads its own first entry), so no load sits behind a branch
+        // Entry row m of this lane sits at int offset 256 m + threadIdx.x of
+        // the tile's rows (list_off with four lanes per particle), so a block
+        // of E rows is one lane base plus constant offsets.  Every lane issues
+        // all E loads (the list allocation has kListPadRows spare rows after
+        // the last tile), so no load sits behind a branch; entries past the
+        // lane's list end become the padding slot.
+        static_assert(TPP == 4 && kTile * TPP == kBlock, "entry offset 256 m + tid");
+        static_assert(E <= kListPadRows, "prefetch beyond the spare rows");
+        const int* lane_rows = s.nbr + (size_t)tile * s.mcap * (kTile * 4) + threadIdx.x;
         auto load_block = [&](int m0, int (&en)[E]) {
+            const int* bp = lane_rows + (size_t)m0 * (kTile * 4);
 #pragma unroll
             for (int m = 0; m < E; m++) {
-                bool ok = m0 + m < mine;
-                int v = __builtin_nontemporal_load(nb + list_off(ok ? q + (m0 + m) * TPP : q));
+                int v = __builtin_nontemporal_load(bp + m * (kTile * 4));
                 // past the end: all slot bits set, clamped to the padding slot;
-                // the value depends on the load either way, so it is never skipped
-                en[m] = min(entry_slot(v) | (ok ? 0 : kSlotMask), cap);
+                // the value depends on the load either way, so the compiler
+                // cannot move the load under a branch
+                en[m] = min(entry_slot(v) | (m0 + m < mine ? 0 : kSlotMask), cap);
             }
         };
         auto eval_block = [&](int m0, const int (&en)[E]) {
@@ -1145,8 +1153,11 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     }
 }
 
+// The staged region limits the pass to three workgroups (three waves per
+// SIMD) per CU, so the register allocator may use that budget to keep the
+// list prefetch in flight instead of aiming at more waves.
 template <int PREC, int TPP, bool KICK, bool ENERGY, bool DRIFT = false>
-__global__ __launch_bounds__(kBlock) void k_vertex_lj(Sys s) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_vertex_lj(Sys s) {
     b_vertex_lj<PREC, TPP, KICK, ENERGY, DRIFT>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
@@ -1870,7 +1881,7 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
         else if (prec == 1) vertex_dispatch<1>(s, kick, false, st);
         else vertex_dispatch<2>(s, kick, false, st);
     } else if (mode == 2) {  // Newton (LJ); with atomics into F it must start at zero
-        launch_half_fill(s, st);
+        (void)launch_half_fill(s, st);  // launch errors surface in hipGetLastError below
         if (s.nrep == 0 && !kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) newton_dispatch<0>(s, st);
         else newton_dispatch<1>(s, st);  // FP32 pair maths, FP64 sums
@@ -1882,7 +1893,7 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
         }
         if (!kick) hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
     } else {
-        launch_half_fill(s, st);
+        (void)launch_half_fill(s, st);  // launch errors surface in hipGetLastError below
         if (!kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) edge_dispatch<0>(s, edge_grid, st);
         else edge_dispatch<1>(s, edge_grid, st);  // FP32 pair maths, FP64 atomics
