@@ -156,10 +156,10 @@ enum BatchClass {
 
 constexpr int kLdsBuckets = 3;
 
-// Largest region capacity (slots) of each LDS bucket: with 32-byte records,
-// bucket 0 leaves room for three workgroups per CU, bucket 1 for two.
+// Largest region capacity (slots) of each LDS bucket: with 24-byte records,
+// bucket 0 leaves room for four workgroups per CU, bucket 1 for three.
 __host__ __device__ inline int bucket_cap(int b) {
-    return b == 0 ? 1664 : (b == 1 ? 2432 : kLdsCapMax);
+    return b == 0 ? 1664 : (b == 1 ? 2240 : kLdsCapMax);
 }
 
 __host__ __device__ inline int lds_bucket(const Sys& s) {

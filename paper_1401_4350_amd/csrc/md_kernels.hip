@@ -541,8 +541,9 @@ __device__ __forceinline__ int tile_lds_base(const int4* seg, int nseg, int cb, 
 // batch are issued by region_issue and consumed by region_store, so a caller
 // can put other loads in between: loads retire in order, so the first batch
 // is issued before slower loads and stored right after them.
-// LDS layout: one 32-byte record (x, y, z, unused) per region slot, so a
-// neighbour is one address and two reads (16 + 8 bytes); slot `cap` is a
+// LDS layout: one packed 24-byte record (x, y, z) per region slot, so a
+// neighbour is one address and two reads (16 + 8 bytes), and the region of a
+// typical tile leaves room for four workgroups per CU; slot `cap` is a
 // padding particle far outside the box.
 // ---------------------------------------------------------------------------
 
@@ -551,7 +552,7 @@ __host__ __device__ __forceinline__ int lds_plane(int cap) { return cap + 8; }
 // Dynamic LDS of the kernels that stage a tile's region (positions), and of
 // those that accumulate over it (three planes of doubles).
 __host__ __device__ __forceinline__ size_t lds_region_bytes(int cap) {
-    return sizeof(double4) * (size_t)lds_plane(cap);
+    return 3 * sizeof(double) * ((size_t)cap + 1);
 }
 __host__ __device__ __forceinline__ size_t lds_acc_bytes(int cap) {
     return 3 * sizeof(double) * (size_t)lds_plane(cap);
@@ -577,22 +578,23 @@ __device__ __forceinline__ void region_issue(const Sys& s, const double4* src, i
     }
 }
 
-__device__ __forceinline__ void region_store(const Sys& s, double4* lds, const RegionBatch& b) {
+__device__ __forceinline__ void region_store(const Sys& s, double* lds, const RegionBatch& b) {
     const int lane = threadIdx.x & (kWave - 1);
 #pragma unroll
     for (int r = 0; r < RegionBatch::R; r++) {
         const int4 d = b.d[r];
         if (d.w >= 0 && lane < d.y - d.x) {
             // the chunk's periodic image is added on the way in
-            lds[d.z + lane] = make_double4(b.p[r].x + (double)((d.w & 3) - 1) * s.box,
-                                           b.p[r].y + (double)(((d.w >> 2) & 3) - 1) * s.box,
-                                           b.p[r].z + (double)(((d.w >> 4) & 3) - 1) * s.box, 0.0);
+            double* q = lds + 3 * (d.z + lane);
+            q[0] = b.p[r].x + (double)((d.w & 3) - 1) * s.box;
+            q[1] = b.p[r].y + (double)(((d.w >> 2) & 3) - 1) * s.box;
+            q[2] = b.p[r].z + (double)(((d.w >> 4) & 3) - 1) * s.box;
         }
     }
 }
 
 // Remaining batches, padding slot and the workgroup barrier.
-__device__ __forceinline__ void region_finish(const Sys& s, const double4* src, double4* lds,
+__device__ __forceinline__ void region_finish(const Sys& s, const double4* src, double* lds,
                                               int cap, int tile, int nchk, int wv,
                                               RegionBatch& rb) {
     constexpr int W = kBlock / kWave;
@@ -600,7 +602,11 @@ __device__ __forceinline__ void region_finish(const Sys& s, const double4* src, 
         region_issue(s, src, tile, nchk, c0, rb);
         region_store(s, lds, rb);
     }
-    if (threadIdx.x == 0) lds[cap] = make_double4(kFar, kFar, kFar, 0.0);
+    if (threadIdx.x == 0) {
+        lds[3 * cap] = kFar;
+        lds[3 * cap + 1] = kFar;
+        lds[3 * cap + 2] = kFar;
+    }
     __syncthreads();
 }
 
@@ -993,13 +999,13 @@ constexpr int kPrefetch = MD_VERTEX_PREFETCH;  // list entries held in registers
 // image.  The cut-off selects a 0/1 factor, so every lane runs the same
 // instruction stream.
 template <int PREC, bool ENERGY>
-__device__ __forceinline__ void lj_lds_term(const Sys& s, const double4* lds, int k,
+__device__ __forceinline__ void lj_lds_term(const Sys& s, const double* lds, int k,
                                             const double4& xi, Acc3<PREC>& f, double& e,
                                             double& w) {
-    const double2 pxy = *reinterpret_cast<const double2*>(&lds[k]);
-    double dx = pxy.x - xi.x;
-    double dy = pxy.y - xi.y;
-    double dz = lds[k].z - xi.z;
+    const double* p = lds + 3 * k;
+    double dx = p[0] - xi.x;
+    double dy = p[1] - xi.y;
+    double dz = p[2] - xi.z;
     double r2 = dx * dx + dy * dy + dz * dz;
     bool in = r2 < s.rc2;
     if (PREC == 0) {
@@ -1041,7 +1047,7 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     static_assert(TPP * kTile == kBlock, "one tile per workgroup");
     static_assert(kPrefetch % 4 == 0, "groups of four");
     static_assert(!DRIFT || KICK, "the drift follows the closing kick");
-    extern __shared__ double4 lds4[];
+    extern __shared__ double lds3[];
     const int tile = bid;
     const int i = tile * kTile + threadIdx.x / TPP;
     const int q = threadIdx.x % TPP;
@@ -1091,14 +1097,14 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
                 if (m0 + m < mmax) {
 #pragma unroll
                     for (int u = 0; u < 4; u++)
-                        lj_lds_term<PREC, ENERGY>(s, lds4, en[m + u], xi, f, e, w);
+                        lj_lds_term<PREC, ENERGY>(s, lds3, en[m + u], xi, f, e, w);
                 }
             }
         };
         int ea[E], eb[E];
         load_block(0, ea);
-        region_store(s, lds4, rb);
-        region_finish(s, s.pos, lds4, cap, tile, nchk, wv, rb);
+        region_store(s, lds3, rb);
+        region_finish(s, s.pos, lds3, cap, tile, nchk, wv, rb);
         // long lists: blocks of E entries, the next block's loads in flight
         // while the current one is evaluated
         for (int m0 = 0; m0 < mmax; m0 += 2 * E) {
@@ -1153,11 +1159,11 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     }
 }
 
-// The staged region limits the pass to three workgroups (three waves per
-// SIMD) per CU, so the register allocator may use that budget to keep the
+// The staged region limits the pass to at most four workgroups (four waves
+// per SIMD) per CU, so the register allocator may use that budget to keep the
 // list prefetch in flight instead of aiming at more waves.
 template <int PREC, int TPP, bool KICK, bool ENERGY, bool DRIFT = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 3))) void k_vertex_lj(Sys s) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_vertex_lj(Sys s) {
     b_vertex_lj<PREC, TPP, KICK, ENERGY, DRIFT>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
