@@ -28,7 +28,7 @@ struct Layout {
     // state offsets
     uint64_t pos, vel, frc, quat, angm, trq, id;
     // workspace offsets
-    uint64_t pos_alt, xbuild, tpos, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
+    uint64_t pos_alt, xbuild, tpos, tposf, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
         ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, epart, wpart, kpart, red, ctrl, tile_seg,
         tile_nseg, tile_chunk, tile_nchunk, tile_row0;
     int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
@@ -73,6 +73,22 @@ md_status validate(const md_params* p) {
 
 namespace {
 
+// Band of the FP32 list test around r_v^2.  A record is rounded to FP32 from
+// [0, L), x_i minus an image shift from [-L, 2L), and their difference once
+// more, so a component of the FP32 separation is off by at most
+// delta = u (3L + r) (u = 2^-24, r the separation); the FP32 squared distance
+// then differs from the exact one by at most 2 sqrt(3) r delta + 3 delta^2 +
+// 3u r^2.  With r <= 2 r_v that is E; outside r_v^2 -+ 2E (rounded outwards)
+// the FP32 result decides as the exact one does.
+void list_test_band(double box, double rv, float* lo, float* hi) {
+    const double u = std::ldexp(1.0, -24), r = 2.0 * rv;
+    const double delta = u * (3.0 * box + r);
+    const double e = 2.0 * std::sqrt(3.0) * r * delta + 3.0 * delta * delta + 3.0 * u * r * r;
+    const double rv2 = rv * rv;
+    *lo = std::nextafter((float)(rv2 - 2.0 * e), 0.0f);
+    *hi = std::nextafter((float)(rv2 + 2.0 * e), INFINITY);
+}
+
 Layout layout(const md_params& p) {
     Layout L;
     uint64_t n = (uint64_t)p.n;
@@ -111,6 +127,7 @@ Layout layout(const md_params& p) {
     L.pos_alt = take(cur, d4);
     L.xbuild = take(cur, d4);
     L.tpos = take(cur, d4);
+    L.tposf = take(cur, 16 * (n + md::kRunPad));
     L.tvel = take(cur, d4);
     L.tquat = take(cur, patchy ? d4 : 0);
     L.tangm = take(cur, patchy ? d4 : 0);
@@ -268,6 +285,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.cell_inv = L.nc / p->box;
     double rv = p->rcut + p->skin;
     y.rv2 = rv * rv;
+    list_test_band(p->box, rv, &y.rv2_lo, &y.rv2_hi);
     y.rc2 = p->rcut * p->rcut;
     y.disp2 = 0.25 * p->skin * p->skin;
     y.dt = p->dt;
@@ -287,6 +305,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.pos_alt = (double4*)(W + L.pos_alt);
     y.xbuild = (double4*)(W + L.xbuild);
     y.tpos = (double4*)(W + L.tpos);
+    y.tposf = (float4*)(W + L.tposf);
     y.tvel = (double4*)(W + L.tvel);
     y.tquat = patchy ? (double4*)(W + L.tquat) : nullptr;
     y.tangm = patchy ? (double4*)(W + L.tangm) : nullptr;
@@ -700,7 +719,6 @@ BatchLayout batch_layout(const md_batch_params& p) {
     // cell sort: at most nblk blocks per system; tile regions: 4 tiles per block
     c[md::kClsSortTiles] = c[md::kClsParticle] + (tiles + 3) / 4 + smax;
     for (int b = 0; b < md::kLdsBuckets; b++) {
-        c[md::kClsBuild0 + b] = tiles;
         c[md::kClsVertex0 + b] = tiles;
         c[md::kClsEdge0 + b] = 4 * tiles;
     }
@@ -776,7 +794,7 @@ struct md_batch {
     // no admitted system uses (not launched).
     void grids(bool bucket, int* out) const {
         for (int c = 0; c < md::kNumClasses; c++) {
-            bool bucketed = c >= md::kClsBuild0;
+            bool bucketed = c >= md::kClsVertex0;
             if (bucketed && used[c] == 0) {
                 out[c] = 0;
                 continue;
@@ -1027,7 +1045,7 @@ md_status md_batch_info(const md_batch* b, md_batch_info_t* out) {
     out->active = b->active;
     int cap = 0;  // largest LDS bucket in use
     for (int bk = 0; bk < md::kLdsBuckets; bk++)
-        if (b->used[md::kClsBuild0 + bk] > 0) cap = md::bucket_cap(bk);
+        if (b->used[md::kClsVertex0 + bk] > 0) cap = md::bucket_cap(bk);
     out->lds_cap = cap;
     out->particles = b->particles;
     out->bytes = b->bytes;

@@ -22,6 +22,7 @@ constexpr int kSegMax = 36;
 constexpr int kChunkMax = 96;
 constexpr int kLdsCapMax = 4096;  // particles per tile region (3 doubles each)
 constexpr int kListPadRows = 32;  // spare list rows after the last tile (prefetch reads)
+constexpr int kRunPad = 8;        // spare records after the FP32 position copy (list-build reads)
 
 // Device-resident control block (one per system).  Written by kernels, read by
 // the host only at syncing calls.
@@ -66,6 +67,7 @@ struct Sys {
     long long max_half;  // half-list capacity (entries)
     double box, inv_box, cell_inv;  // L, 1/L, nc/L
     double rv2;     // (r_c + r_s)^2
+    float rv2_lo, rv2_hi;  // FP32 list test: below lo in, from hi out, between FP64 decides
     double rc2;     // r_c^2
     double disp2;   // (r_s/2)^2
     double dt, hdt, inv_mass, inv_inertia;
@@ -87,6 +89,7 @@ struct Sys {
     double4* pos_alt;  // second position buffer (vertex pass with the next drift)
     double4* xbuild;
     double4* tpos;
+    float4* tposf;   // FP32 copy of tpos (list-build test)
     double4* tvel;
     double4* tquat;
     double4* tangm;
@@ -142,9 +145,6 @@ enum BatchClass {
     // few small-box systems with large regions do not lower the occupancy of
     // all the others.  A system's blocks go to the bucket of its region
     // capacity (lds_bucket); its count in the other two is zero.
-    kClsBuild0,        // list build: ntiles
-    kClsBuild1,
-    kClsBuild2,
     kClsVertex0,       // vertex pass: LJ ntiles, patchy nblk
     kClsVertex1,
     kClsVertex2,
@@ -187,8 +187,6 @@ __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
         case kClsParticle: return s.nblk;
         case kClsTile: return s.ntiles;
         case kClsSortTiles: return sort_blocks(s) + (s.ntiles + kBlock / kWave - 1) / (kBlock / kWave);
-        case kClsBuild0: case kClsBuild1: case kClsBuild2:
-            return lds_bucket(s) == cls - kClsBuild0 ? s.ntiles : 0;
         case kClsVertex0: case kClsVertex1: case kClsVertex2:
             return lds_bucket(s) == cls - kClsVertex0 ? (s.pot == 0 ? s.ntiles : s.nblk) : 0;
         default:

@@ -400,9 +400,11 @@ __device__ __forceinline__ void b_cell_sort(const Sys& s, int bid, int nb) {
             }
             if (k0 + lane < m) {  // the particle in previous slot p takes slot b + rank
                 const int q = b + rank;
-                double4 x = s.pos[p];
-                s.tpos[q] = make_double4(wrap_box(x.x, s.box), wrap_box(x.y, s.box),
-                                         wrap_box(x.z, s.box), 0.0);
+                const double4 x = s.pos[p];
+                const double wx = wrap_box(x.x, s.box), wy = wrap_box(x.y, s.box),
+                             wz = wrap_box(x.z, s.box);
+                s.tpos[q] = make_double4(wx, wy, wz, 0.0);
+                s.tposf[q] = make_float4((float)wx, (float)wy, (float)wz, 0.f);
                 s.tvel[q] = s.vel[p];
                 s.tid[q] = s.id[p];
                 if (s.pot == 1) {
@@ -611,14 +613,14 @@ __device__ __forceinline__ void region_finish(const Sys& s, const double4* src, 
 }
 
 // ---------------------------------------------------------------------------
-// Verlet-list build: one workgroup per tile, four lanes per particle.  The
-// four lanes of particle i scan each of its 27 neighbour cells four
-// candidates at a time (positions from the tile's LDS image when staged, in
-// FP64, from the global reorder buffer otherwise) and keep every j != i with
-// r_ij^2 < r_v^2.  Accepted candidates are compacted into i's list with a
-// wavefront ballot, so the list order (cell order, then slot) is fixed.
-// Staged entries index the LDS image; the others are slots.  The build also
-// moves the particle records from the reorder buffer back into the state and
+// Verlet-list build: one lane per particle, one wavefront per tile (four
+// tiles per workgroup).  The lane walks its particle's 27 neighbour cells as
+// runs of consecutive slots (one or two per row of cells) in FP64 from the
+// reorder buffer and appends every j != i with r_ij^2 < r_v^2 to its list, so
+// the list order (cell order, then slot) is fixed.  A staged tile takes each
+// run in its periodic image and stores entries that index the tile's region;
+// the others store slots with the minimum-image code.  The build also moves
+// the particle records from the reorder buffer back into the state and
 // stores the build reference positions; per-tile totals of the half-list
 // lengths (entries with j > i) feed the half-list offsets.
 // ---------------------------------------------------------------------------
@@ -641,20 +643,17 @@ __device__ __forceinline__ void scan_tiles(const Sys& s) {
 
 __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
-    __shared__ int red[kBlock / kWave];
-    constexpr int TPP = kTileTpp;
-    const int tile = bid;
-    const int i = tile * kTile + threadIdx.x / TPP;
-    const int q = threadIdx.x % TPP;
     const int lane = threadIdx.x & (kWave - 1);
-    const int gshift = lane & ~(TPP - 1);  // first lane of this particle's group
+    const int tile = bid * (kBlock / kWave) + (int)threadIdx.x / kWave;  // wavefront-uniform
+    const int i = bid * kBlock + threadIdx.x;  // = tile * kTile + lane
     const bool act = i < s.n;
     const int ii = act ? i : s.n - 1;
-    const int nseg = s.tile_nseg[tile];
+    const bool tact = tile < s.ntiles;
+    const int nseg = tact ? s.tile_nseg[tile] : -1;
     const int row0 = nseg >= 0 ? s.tile_row0[tile] : 0;
-    const int4* seg = s.tile_seg + (size_t)tile * kSegMax;
+    const int4* seg = s.tile_seg + (size_t)(tact ? tile : 0) * kSegMax;
     const double4 xi = s.tpos[ii];
-    if (act && q == 0) {
+    if (act) {
         s.pos[i] = xi;
         s.xbuild[i] = xi;
         s.vel[i] = s.tvel[i];
@@ -670,15 +669,33 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     const int cz = cell_coord(xi.z, s.cell_inv, nc);
     const int span = nc >= 3 ? 3 : nc;  // distinct cells per dimension
     const int lo = nc >= 3 ? -1 : 0;
-    int* row = list_row_w(s, ii);
+    int4* wrow = (int4*)list_row_w(s, ii);  // the particle's current row of four entries
+    const int cap = s.cap;
+    const double rv2 = s.rv2;
     int count = 0, half = 0;
+    int e0 = 0, e1 = 0, e2 = 0;  // entries of the current row not yet written
+    // Appends entry `ent` for partner j; a row of four goes out in one store.
+    auto append = [&](int j, int ent) {
+        if (count < cap) {
+            const int sl = count & 3;
+            if (sl == 3) {
+                *wrow = make_int4(e0, e1, e2, ent);
+                wrow += kTile;
+            }
+            e0 = sl == 0 ? ent : e0;
+            e1 = sl == 1 ? ent : e1;
+            e2 = sl == 2 ? ent : e2;
+            half += j > i;
+        }
+        count++;
+    };
     for (int dz = 0; dz < span; dz++) {
         int az = cz + lo + dz;
-        int wz = az < 0 ? 0 : (az >= nc ? 2 : 1);  // image of the cell row
+        const int wz = az < 0 ? 0 : (az >= nc ? 2 : 1);  // image of the cell row
         az = az < 0 ? az + nc : (az >= nc ? az - nc : az);
         for (int dy = 0; dy < span; dy++) {
             int ay = cy + lo + dy;
-            int wy = ay < 0 ? 0 : (ay >= nc ? 2 : 1);
+            const int wy = ay < 0 ? 0 : (ay >= nc ? 2 : 1);
             ay = ay < 0 ? ay + nc : (ay >= nc ? ay - nc : ay);
             // The neighbour cells of this row in list order (dx ascending) as
             // runs of consecutive cells, i.e. of consecutive slots: one run
@@ -702,88 +719,90 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                 const int xa = run ? a1 : a0, xb = run ? b1 : b0, wx = run ? w1 : w0;
                 const int cb = act ? s.cstart[rowbase + xa] : 0;
                 const int ce = act ? s.cstart[rowbase + xb + 1] : 0;
+                if (cb >= ce) continue;
                 const int code = wx | wy << 2 | wz << 4;
-                // the run's periodic image, added as the region copy adds it
-                const double shx = (double)(wx - 1) * s.box, shy = (double)(wy - 1) * s.box,
-                             shz = (double)(wz - 1) * s.box;
-                int base = -1;
-                if (nseg >= 0 && cb < ce) {
-                    // the two fixed segment slots of (home row, dz, dy)
+                if (nseg >= 0) {
+                    // Staged tile: the entry indexes the tile's region, found
+                    // in the two fixed segment slots of (home row, dz, dy).
+                    // Candidates are taken in the run's periodic image, i.e.
+                    // against x_i minus the image shift.
                     const int hr = cz * nc + cy - row0;
                     const int4* sg = seg + ((hr * 3 + dz) * 3 + dy) * 2;
-                    base = (hr == 0 || hr == 1) ? tile_lds_base(sg, 2, cb, code) : -1;
+                    const int base = (hr == 0 || hr == 1) ? tile_lds_base(sg, 2, cb, code) : -1;
                     if (base < 0) atomicOr(&s.ctrl->overflow, 2);  // region misses a cell
-                }
-                // candidate j with its record pj (loaded by the caller)
-                auto consider = [&](int j, const double4& pj) {
-                    const bool cand = j < ce && j != i;
-                    double r2 = 1e300;
-                    int ent = 0;
-                    if (cand) {
-                        if (nseg >= 0) {
-                            int m = max(base, 0) + (j - cb);
-                            double ex = (pj.x + shx) - xi.x, ey = (pj.y + shy) - xi.y,
-                                   ez = (pj.z + shz) - xi.z;
-                            r2 = ex * ex + ey * ey + ez * ez;
-                            ent = m | code << kSlotBits;
-                        } else {
-                            double ex = pj.x - xi.x, ey = pj.y - xi.y, ez = pj.z - xi.z;
-                            double ddx = wrap_delta(ex, s.box, s.inv_box);
-                            double ddy = wrap_delta(ey, s.box, s.inv_box);
-                            double ddz = wrap_delta(ez, s.box, s.inv_box);
-                            r2 = ddx * ddx + ddy * ddy + ddz * ddz;
-                            ent = j | (image_code(ex, s.inv_box) | image_code(ey, s.inv_box) << 2 |
-                                       image_code(ez, s.inv_box) << 4)
-                                          << kSlotBits;
+                    const double sx = xi.x - (double)(wx - 1) * s.box;
+                    const double sy = xi.y - (double)(wy - 1) * s.box;
+                    const double sz = xi.z - (double)(wz - 1) * s.box;
+                    const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
+                    const int eoff = (max(base, 0) - cb) + (code << kSlotBits);
+                    // The test runs in FP32 on the rounded copy of the records;
+                    // where its result lies within the band around r_v^2 that
+                    // bounds its rounding error, FP64 decides, so the list is
+                    // the one the FP64 test gives.
+                    auto consider = [&](int j, const float4& pf) {
+                        const float ex = pf.x - fx, ey = pf.y - fy, ez = pf.z - fz;
+                        const float r2 = ex * ex + ey * ey + ez * ez;
+                        bool in = r2 < s.rv2_lo;
+                        if (r2 >= s.rv2_lo && r2 < s.rv2_hi) {
+                            const double4 pj = s.tpos[j];
+                            const double dx = pj.x - sx, dy = pj.y - sy, dz = pj.z - sz;
+                            in = dx * dx + dy * dy + dz * dz < rv2;
                         }
+                        if (j < ce && j != i && in) append(j, eoff + j);
+                    };
+                    // Four candidates per round; the next round's loads are
+                    // issued before this round is tested, so that they are in
+                    // flight meanwhile (reads past the run's end land in the
+                    // copy or its spare records and are not used).
+                    const float4* pr = s.tposf + cb;
+                    float4 q0 = pr[0], q1 = pr[1], q2 = pr[2], q3 = pr[3];
+                    for (int j0 = cb; j0 < ce; j0 += 4) {
+                        const float4 p0 = q0, p1 = q1, p2 = q2, p3 = q3;
+                        pr += 4;
+                        q0 = pr[0], q1 = pr[1], q2 = pr[2], q3 = pr[3];
+                        consider(j0 + 0, p0);
+                        consider(j0 + 1, p1);
+                        consider(j0 + 2, p2);
+                        consider(j0 + 3, p3);
                     }
-                    const bool keep = cand && r2 < s.rv2;
-                    const unsigned long long bal = __ballot(keep);
-                    const unsigned grp = (unsigned)(bal >> gshift) & ((1u << TPP) - 1);
-                    const unsigned balh = (unsigned)(__ballot(keep && j > i) >> gshift) &
-                                          ((1u << TPP) - 1);
-                    const int k = count + __builtin_popcount(grp & ((1u << q) - 1));
-                    if (keep && k < s.cap) row[list_off(k)] = ent;
-                    // half entries among the stored ones (k < cap)
-                    const int nk = __builtin_popcount(grp);
-                    if (count + nk <= s.cap) {
-                        half += __builtin_popcount(balh);
-                    } else {
-                        for (int l = 0; l < TPP; l++)
-                            if ((balh >> l) & 1) {
-                                int kl = count + __builtin_popcount(grp & ((1u << l) - 1));
-                                half += kl < s.cap;
-                            }
+                } else {
+                    // Global gathers: slot entries with the minimum-image code.
+                    auto consider = [&](int j, const double4& pj) {
+                        const double ex = pj.x - xi.x, ey = pj.y - xi.y, ez = pj.z - xi.z;
+                        const double ddx = wrap_delta(ex, s.box, s.inv_box);
+                        const double ddy = wrap_delta(ey, s.box, s.inv_box);
+                        const double ddz = wrap_delta(ez, s.box, s.inv_box);
+                        const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                        if (j < ce && j != i && r2 < rv2)
+                            append(j, j | (image_code(ex, s.inv_box) | image_code(ey, s.inv_box) << 2 |
+                                           image_code(ez, s.inv_box) << 4)
+                                              << kSlotBits);
+                    };
+                    for (int j0 = cb; j0 < ce; j0 += 2) {
+                        const double4 p0 = s.tpos[min(j0 + 0, ce - 1)];
+                        const double4 p1 = s.tpos[min(j0 + 1, ce - 1)];
+                        consider(j0 + 0, p0);
+                        consider(j0 + 1, p1);
                     }
-                    count += nk;
-                };
-                // two candidates per lane per round, both loads issued first
-                // (unconditionally, clamped into the run) so that they overlap
-                for (int j0 = cb; j0 < ce; j0 += 2 * TPP) {
-                    const int ja = j0 + q, jb = ja + TPP;
-                    const double4 pa = s.tpos[min(ja, ce - 1)];
-                    const double4 pb = s.tpos[min(jb, ce - 1)];
-                    consider(ja, pa);
-                    consider(jb, pb);
                 }
             }
         }
     }
-    if (act && q == 0) {
-        s.ncount[i] = count < s.cap ? count : s.cap;
+    if (act && (min(count, cap) & 3)) *wrow = make_int4(e0, e1, e2, 0);  // last, partial row
+    if (act) {
+        s.ncount[i] = count < cap ? count : cap;
         s.hcount[i] = half;
-        if (count > s.cap) atomicOr(&s.ctrl->overflow, 1);
-        atomicMax(&s.ctrl->max_count, count);
+        if (count > cap) atomicOr(&s.ctrl->overflow, 1);
     }
-    // tile total of half-list lengths (one lane per particle contributes)
-    int v = act && q == 0 ? half : 0;
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off);
-    if (lane == 0) red[threadIdx.x / kWave] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < kBlock / kWave; w++) t += red[w];
-        s.bsum[tile] = t;
+    // wavefront (= tile) totals: longest list and half-list length
+    int mx = act ? count : 0, hs = act ? half : 0;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        mx = max(mx, __shfl_xor(mx, off));
+        hs += __shfl_xor(hs, off);
+    }
+    if (lane == 0 && tact) {
+        atomicMax(&s.ctrl->max_count, mx);
+        s.bsum[tile] = hs;
     }
     if (last_block(&s.ctrl->done_build, nb)) scan_tiles(s);
 }
@@ -1808,7 +1827,7 @@ hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) 
         hipLaunchKernelGGL(k_sort_tiles, dim3((unsigned)class_blocks(s, kClsSortTiles)),
                            dim3(kBlock), 0, st, s);
     }
-    if (lists) hipLaunchKernelGGL(k_build, dim3(s.ntiles), dim3(kBlock), 0, st, s);
+    if (lists) hipLaunchKernelGGL(k_build, dim3(s.nblk), dim3(kBlock), 0, st, s);
     return hipGetLastError();
 }
 
@@ -1995,9 +2014,8 @@ __global__ __launch_bounds__(kBlock) void kb_sort_tiles(BatchDev b, int step) {
     });
 }
 
-template <int C>
 __global__ __launch_bounds__(kBlock) void kb_build(BatchDev b, int step) {
-    batch_block<C>(b, step, [](const Sys& s, int lb) { b_build(s, lb, s.ntiles); });
+    batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_build(s, lb, s.nblk); });
 }
 
 __global__ __launch_bounds__(kBlock) void kb_half_fill(BatchDev b, int step) {
@@ -2065,11 +2083,7 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
         hipLaunchKernelGGL(kb_cell_bin, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_cell_scatter, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_sort_tiles, g(kClsSortTiles), blk, 0, st, b, k);
-        per_bucket([&](auto bk) {
-            constexpr int B = decltype(bk)::value;
-            if (grid[kClsBuild0 + B] > 0)
-                hipLaunchKernelGGL(kb_build<kClsBuild0 + B>, g(kClsBuild0 + B), blk, 0, st, b, k);
-        });
+        hipLaunchKernelGGL(kb_build, g(kClsParticle), blk, 0, st, b, k);
         if (mode == 0) {
             per_bucket([&](auto bk) {
                 constexpr int B = decltype(bk)::value;
