@@ -29,7 +29,7 @@ struct Layout {
     uint64_t pos, vel, frc, quat, angm, trq, id;
     // workspace offsets
     uint64_t pos_alt, xbuild, tpos, tposf, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
-        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, epart, wpart, kpart, red, ctrl, tile_seg,
+        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, tmax, sync, epart, wpart, kpart, red, ctrl, tile_seg,
         tile_nseg, tile_chunk, tile_nchunk, tile_row0;
     int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
     long long max_half = 0;
@@ -76,17 +76,18 @@ namespace {
 // Band of the FP32 list test around r_v^2.  A record is rounded to FP32 from
 // [0, L), x_i minus an image shift from [-L, 2L), and their difference once
 // more, so a component of the FP32 separation is off by at most
-// delta = u (3L + r) (u = 2^-24, r the separation); the FP32 squared distance
-// then differs from the exact one by at most 2 sqrt(3) r delta + 3 delta^2 +
-// 3u r^2.  With r <= 2 r_v that is E; outside r_v^2 -+ 2E (rounded outwards)
-// the FP32 result decides as the exact one does.
-void list_test_band(double box, double rv, float* lo, float* hi) {
+// delta = u (3L + r) (u = 2^-24, r the separation); the FP32 value of
+// r^2 - lo (three fused multiply-adds) then differs from the exact one by at
+// most 2 sqrt(3) r delta + 3 delta^2 + 3u max(r^2, lo).  With r <= 2 r_v that
+// is E; below lo = r_v^2 - 2E and from lo + band >= r_v^2 + 2E on (both
+// rounded outwards) the FP32 result decides as the exact one does.
+void list_test_band(double box, double rv, float* lo, float* band) {
     const double u = std::ldexp(1.0, -24), r = 2.0 * rv;
     const double delta = u * (3.0 * box + r);
     const double e = 2.0 * std::sqrt(3.0) * r * delta + 3.0 * delta * delta + 3.0 * u * r * r;
     const double rv2 = rv * rv;
     *lo = std::nextafter((float)(rv2 - 2.0 * e), 0.0f);
-    *hi = std::nextafter((float)(rv2 + 2.0 * e), INFINITY);
+    *band = std::nextafter((float)(rv2 + 2.0 * e - (double)*lo), INFINITY);
 }
 
 Layout layout(const md_params& p) {
@@ -147,6 +148,8 @@ Layout layout(const md_params& p) {
     L.rep = take(cur, p.pot == MD_POT_LJ ? 32 * n * (uint64_t)p.newton_m : 0);
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
     L.bsum = take(cur, 4 * (uint64_t)std::max(L.nblk, L.ntiles));  // per-tile half totals
+    L.tmax = take(cur, 4 * (uint64_t)L.ntiles);
+    L.sync = take(cur, 4 * (uint64_t)md::kSyncUses * md::kSyncInts);
     L.tile_seg = take(cur, 16 * (uint64_t)L.ntiles * md::kSegMax);
     L.tile_nseg = take(cur, 4 * (uint64_t)L.ntiles);
     L.tile_chunk = take(cur, 16 * (uint64_t)L.ntiles * md::kChunkMax);
@@ -285,7 +288,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.cell_inv = L.nc / p->box;
     double rv = p->rcut + p->skin;
     y.rv2 = rv * rv;
-    list_test_band(p->box, rv, &y.rv2_lo, &y.rv2_hi);
+    list_test_band(p->box, rv, &y.rv2_lo, &y.rv2_band);
     y.rc2 = p->rcut * p->rcut;
     y.disp2 = 0.25 * p->skin * p->skin;
     y.dt = p->dt;
@@ -325,6 +328,8 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.nrep = p->pot == MD_POT_LJ ? p->newton_m : 0;
     y.chunk_row = (int*)(W + L.chunk_row);
     y.bsum = (int*)(W + L.bsum);
+    y.tmax = (int*)(W + L.tmax);
+    y.sync = (int*)(W + L.sync);
     y.ntiles = L.ntiles;
     y.lds_cap = L.lds_cap;
     y.tile_seg = (int4*)(W + L.tile_seg);

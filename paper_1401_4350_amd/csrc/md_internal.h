@@ -22,7 +22,7 @@ constexpr int kSegMax = 36;
 constexpr int kChunkMax = 96;
 constexpr int kLdsCapMax = 4096;  // particles per tile region (3 doubles each)
 constexpr int kListPadRows = 32;  // spare list rows after the last tile (prefetch reads)
-constexpr int kRunPad = 8;        // spare records after the FP32 position copy (list-build reads)
+constexpr int kRunPad = 16;       // spare records after the FP32 position copy (list-build reads)
 
 // Device-resident control block (one per system).  Written by kernels, read by
 // the host only at syncing calls.
@@ -32,15 +32,24 @@ struct Ctrl {
     int nonfinite;      // sticky: a force or position was NaN/Inf
     int max_count;      // longest full list at the last build
     int staged;         // tiles of the last build whose region fits in LDS
-    int done_bin;       // workgroups of the cell binning that have finished
+    int pad0;
     long long npairs;   // half-list entries at the last build (clamped to capacity)
     long long rebuilds; // number of builds
-    int done_build;     // workgroups of the list build that have finished
     int half_stale;     // the half list predates the last build (filled on demand)
-    int done_half;      // workgroups of the half-list fill that have finished
     int pad1;
     long long pad[2];
 };
+
+// Completion counters of the kernels whose last workgroup runs an epilogue
+// (a scan).  Atomics on one address serialise (about 12 ns each on this
+// chip), so workgroup b counts in sub-counter b % kSyncFan (kSyncStride ints
+// apart) and the last of each group in a top counter: no counter takes more
+// than max(ceil(nb / kSyncFan), kSyncFan) atomics.  All counters are zero
+// between launches.
+constexpr int kSyncFan = 64;
+constexpr int kSyncStride = 16;
+constexpr int kSyncInts = (kSyncFan + 1) * kSyncStride;
+enum SyncUse { kSyncBin = 0, kSyncBuild, kSyncHalf, kSyncUses };
 
 // Pair-potential constants in the arithmetic type of the pair maths.
 template <typename R>
@@ -67,7 +76,7 @@ struct Sys {
     long long max_half;  // half-list capacity (entries)
     double box, inv_box, cell_inv;  // L, 1/L, nc/L
     double rv2;     // (r_c + r_s)^2
-    float rv2_lo, rv2_hi;  // FP32 list test: below lo in, from hi out, between FP64 decides
+    float rv2_lo, rv2_band;  // FP32 list test: below lo in, from lo + band out, between FP64 decides
     double rc2;     // r_c^2
     double disp2;   // (r_s/2)^2
     double dt, hdt, inv_mass, inv_inertia;
@@ -109,6 +118,8 @@ struct Sys {
     int nrep;
     int* chunk_row;  // first row of every 64-pair chunk of the half list
     int* bsum;       // per-block half counts, then offsets
+    int* tmax;       // per-tile longest full list of the last build
+    int* sync;       // [kSyncUses * kSyncInts] completion counters
     int ntiles;      // ceil(n / kTile)
     int lds_cap;     // region capacity (particles) of a tile staged in LDS
     int4* tile_seg;  // [ntiles * kSegMax]: (slot begin, slot end, LDS base, image code)
@@ -139,7 +150,7 @@ constexpr int kRedBlocks = 1024;
 enum BatchClass {
     kClsParticle = 0,  // nblk = ceil(n / kBlock)
     kClsTile,          // ntiles (one block per tile of kTile slots)
-    kClsSortTiles,     // sort_blocks + ceil(ntiles / 4): cell sort, then a wavefront per tile
+    kClsSortTiles,     // nblk + ceil(ntiles / 4): cell sort, then a wavefront per tile
     // Kernels that stage or accumulate over a tile's region in LDS come in
     // three LDS buckets, each launched with its own fixed dynamic LDS, so a
     // few small-box systems with large regions do not lower the occupancy of
@@ -174,12 +185,8 @@ struct BatchDev {
     int nslots;
 };
 
-// Workgroups of the cell sort: one wavefront per cell, striding over the
-// cells beyond nblk workgroups.
-__host__ __device__ inline int sort_blocks(const Sys& s) {
-    int full = (int)(((long long)s.ncell * kWave + kBlock - 1) / kBlock);
-    return full < s.nblk ? full : s.nblk;
-}
+// Workgroups of the cell sort: one lane per particle.
+__host__ __device__ inline int sort_blocks(const Sys& s) { return s.nblk; }
 
 // Blocks a system takes in a class.
 __host__ __device__ inline int class_blocks(const Sys& s, int cls) {

@@ -242,73 +242,80 @@ __device__ __forceinline__ void patchy_pair(const V3<double>& d, double r2, cons
 
 __global__ void k_set_rebuild(Ctrl* c) { c->rebuild = 1; }
 
-__global__ void k_clear_ctrl(Ctrl* c) {
+__global__ void k_clear_ctrl(Ctrl* c, int* sync) {
+    for (int k = threadIdx.x; k < kSyncUses * kSyncInts; k += blockDim.x) sync[k] = 0;
+    if (threadIdx.x != 0) return;
     c->rebuild = 0;
     c->overflow = 0;
     c->nonfinite = 0;
     c->max_count = 0;
     c->staged = 0;
-    c->done_bin = 0;
     c->npairs = 0;
     c->rebuilds = 0;
-    c->done_build = 0;
     c->half_stale = 0;
-    c->done_half = 0;
 }
 
 // True in the one workgroup, of the nb that call this with the same counter,
 // that arrives last; that workgroup then sees the device-scope atomics and
 // agent-scope stores every other one made before arriving.  Resets the
 // counter for its next use.  Every thread of the workgroup must call it.
-__device__ __forceinline__ bool last_block(int* counter, int nb) {
+// True in the workgroup that finishes last of nb (workgroup bid of 0 .. nb-1).
+// Two-level count over the counters `cnt` (kSyncInts ints, zero before and
+// after).  It orders nothing beyond the count: a per-workgroup cache
+// writeback (a device-scope release) costs about 20 ns per workgroup,
+// serialised, so data the last workgroup reads from the others travels only
+// through device-coherent accesses: atomic read-modify-writes, or
+// device-scope atomic stores, which are complete once the barrier below has
+// waited for the workgroup's memory operations, read back with device-scope
+// atomic loads (coh_load).  Plain stores are seen by later kernels only.
+__device__ __forceinline__ bool last_block(int* cnt, int bid, int nb) {
     __shared__ int is_last;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();  // release this workgroup's writes
-        int prev = atomicAdd(counter, 1);
-        is_last = prev == nb - 1;
-        if (is_last) atomicExch(counter, 0);
+        const int g = bid % kSyncFan;
+        const int members = (nb - 1 - g) / kSyncFan + 1;  // workgroups of group g
+        int last = 0;
+        if (atomicAdd(&cnt[g * kSyncStride], 1) == members - 1) {
+            atomicExch(&cnt[g * kSyncStride], 0);
+            const int groups = nb < kSyncFan ? nb : kSyncFan;
+            if (atomicAdd(&cnt[kSyncFan * kSyncStride], 1) == groups - 1) {
+                atomicExch(&cnt[kSyncFan * kSyncStride], 0);
+                last = 1;
+            }
+        }
+        is_last = last;
     }
     __syncthreads();
-    if (!is_last) return false;
-    __threadfence();  // acquire the others'
-    return true;
+    return is_last;
 }
 
-
+// Device-coherent store and load of an int (for last_block's epilogues).
+__device__ __forceinline__ void coh_store(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int coh_load(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ---------------------------------------------------------------------------
 // Cell-list counting sort.  Every kernel returns at once unless a rebuild is
 // due, so the sequence can sit in every step without a host round trip.
 // ---------------------------------------------------------------------------
 
-// Exclusive prefix sum of a[0, len) by one workgroup: emit(k, sum of
-// a[0, k), a[k]) for every k, in chunks of kBlock * 16 elements (each thread
-// sixteen consecutive ones, read as four 16-byte loads; `a` is 16-byte
-// aligned).  Returns the total.
-template <typename Emit>
-__device__ __forceinline__ long long block_scan(const int* a, int len, Emit emit) {
-    constexpr int V = 16;
+// Exclusive prefix sum of a[0, len) by one workgroup, a[k] = load(k):
+// emit(k, sum of a[0, k), a[k]) for every k, in chunks of kBlock * V
+// elements (each thread V consecutive ones, all loads issued first).
+// Returns the total.
+template <int V, typename Load, typename Emit>
+__device__ __forceinline__ long long block_scan(int len, Load load, Emit emit) {
     __shared__ long long sh[kBlock];
     const int t = threadIdx.x;
     long long base = 0;
     for (int c0 = 0; c0 < len; c0 += kBlock * V) {
         const int k0 = c0 + t * V;
         int v[V];
-        if (k0 + V <= len) {
-            const int4* q = reinterpret_cast<const int4*>(a + k0);
 #pragma unroll
-            for (int u = 0; u < V / 4; u++) {
-                int4 w = q[u];
-                v[4 * u] = w.x;
-                v[4 * u + 1] = w.y;
-                v[4 * u + 2] = w.z;
-                v[4 * u + 3] = w.w;
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < V; u++) v[u] = k0 + u < len ? a[k0 + u] : 0;
-        }
+        for (int u = 0; u < V; u++) v[u] = k0 + u < len ? load(k0 + u) : 0;
         long long sum = 0;
 #pragma unroll
         for (int u = 0; u < V; u++) sum += v[u];
@@ -335,34 +342,51 @@ __device__ __forceinline__ long long block_scan(const int* a, int len, Emit emit
 // Exclusive scan of the cell counts into cell_start by one workgroup; the
 // counts are cleared for the next build.
 __device__ __forceinline__ void scan_cells(const Sys& s) {
-    const long long tot = block_scan(s.ccount, s.ncell, [&](int k, long long run, int) {
-        s.cstart[k] = (int)run;
-        s.ccount[k] = 0;
-    });
-    if (threadIdx.x == 0) {
-        s.cstart[s.ncell] = (int)tot;
-        // the list build that follows records its maximum and staged tiles
-        s.ctrl->max_count = 0;
-        s.ctrl->staged = 0;
-    }
+    // the counts come from atomics; reading them by exchange also clears
+    // them for the next build
+    const long long tot = block_scan<32>(
+        s.ncell, [&](int k) { return atomicExch(&s.ccount[k], 0); },
+        [&](int k, long long run, int) { s.cstart[k] = (int)run; });
+    if (threadIdx.x == 0) s.cstart[s.ncell] = (int)tot;
 }
 
 // Bins every particle into its cell (counts by atomics; the atomic's return
 // value is the particle's provisional rank in the cell); the workgroup that
-// finishes last scans the counts into cell starts.
+// finishes last scans the counts into cell starts.  Lanes of a wavefront in
+// the same cell share one atomic (particles arrive in slot order, so a
+// wavefront holds few cells): one add of their number, then ranks by lane
+// order.
 __device__ __forceinline__ void b_cell_bin(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     const int p = bid * kBlock + threadIdx.x;
+    const int lane = threadIdx.x & (kWave - 1);
+    int c = -1;
     if (p < s.n) {
-        double4 x = s.pos[p];
-        int cx = cell_coord(wrap_box(x.x, s.box), s.cell_inv, s.nc);
-        int cy = cell_coord(wrap_box(x.y, s.box), s.cell_inv, s.nc);
-        int cz = cell_coord(wrap_box(x.z, s.box), s.cell_inv, s.nc);
-        int c = (cz * s.nc + cy) * s.nc + cx;
+        const double4 x = s.pos[p];
+        const int cx = cell_coord(wrap_box(x.x, s.box), s.cell_inv, s.nc);
+        const int cy = cell_coord(wrap_box(x.y, s.box), s.cell_inv, s.nc);
+        const int cz = cell_coord(wrap_box(x.z, s.box), s.cell_inv, s.nc);
+        c = (cz * s.nc + cy) * s.nc + cx;
         s.cell[p] = c;
-        s.rank[p] = atomicAdd(&s.ccount[c], 1);
     }
-    if (last_block(&s.ctrl->done_bin, nb)) scan_cells(s);
+    // group the lanes by cell (no memory traffic), then one atomic per group,
+    // all groups at once
+    const unsigned long long below = (1ull << lane) - 1;
+    unsigned long long todo = __ballot(c >= 0);
+    int lead = lane, idx = 0, size = 0;
+    while (todo) {
+        const int l = __builtin_ctzll(todo);
+        const int cl = __builtin_amdgcn_readlane(c, l);
+        const unsigned long long same = __ballot(c == cl);
+        if (c == cl) lead = l, idx = __builtin_popcountll(same & below);
+        if (lane == l) size = __builtin_popcountll(same);
+        todo &= ~same;
+    }
+    int base = 0;
+    if (size > 0) base = atomicAdd(&s.ccount[c], size);
+    base = __shfl(base, lead);
+    if (p < s.n) s.rank[p] = base + idx;
+    if (last_block(s.sync + kSyncBin * kSyncInts, bid, nb)) scan_cells(s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) { b_cell_bin(s, blockIdx.x, gridDim.x); }
@@ -378,41 +402,35 @@ __global__ __launch_bounds__(kBlock) void k_cell_scatter(Sys s) {
     b_cell_scatter(s, blockIdx.x, gridDim.x);
 }
 
-// One wavefront per cell puts the cell's members (scattered in atomic order)
-// in ascending order of their previous slot, so the slot order, and every sum
-// over a list, does not depend on atomic timing.  A member's rank is the
-// number of members with a smaller previous slot, counted with lane reads
-// over the cell (64 members at a time).  Each member's records (position
-// wrapped into the box, velocity, id, orientation) are copied to the reorder
-// buffers at its new slot.
-__device__ __forceinline__ void b_cell_sort(const Sys& s, int bid, int nb) {
-    const int lane = threadIdx.x & (kWave - 1);
-    constexpr int kWaves = kBlock / kWave;
-    for (int c = bid * kWaves + threadIdx.x / kWave; c < s.ncell; c += nb * kWaves) {
-        const int b = s.cstart[c], m = s.cstart[c + 1] - b;
-        for (int k0 = 0; k0 < m; k0 += kWave) {
-            int p = k0 + lane < m ? s.order[b + k0 + lane] : INT_MAX;
-            int rank = 0;
-            for (int k1 = 0; k1 < m; k1 += kWave) {
-                int o = k1 + lane < m ? s.order[b + k1 + lane] : INT_MAX;
-                int lim = min(kWave, m - k1);
-                for (int l = 0; l < lim; l++) rank += __builtin_amdgcn_readlane(o, l) < p;
-            }
-            if (k0 + lane < m) {  // the particle in previous slot p takes slot b + rank
-                const int q = b + rank;
-                const double4 x = s.pos[p];
-                const double wx = wrap_box(x.x, s.box), wy = wrap_box(x.y, s.box),
-                             wz = wrap_box(x.z, s.box);
-                s.tpos[q] = make_double4(wx, wy, wz, 0.0);
-                s.tposf[q] = make_float4((float)wx, (float)wy, (float)wz, 0.f);
-                s.tvel[q] = s.vel[p];
-                s.tid[q] = s.id[p];
-                if (s.pot == 1) {
-                    s.tquat[q] = s.quat[p];
-                    s.tangm[q] = s.angm[p];
-                }
-            }
-        }
+// One lane per particle puts the members of every cell (scattered in atomic
+// order) in ascending order of their previous slot, so the slot order, and
+// every sum over a list, does not depend on atomic timing: particle p's rank
+// is the number of members of its cell with a smaller previous slot.  Its
+// records (position wrapped into the box, with its FP32 copy, velocity, id,
+// orientation) are copied to the reorder buffers at its new slot.
+__device__ __forceinline__ void b_cell_sort(const Sys& s, int bid) {
+    const int p = bid * kBlock + threadIdx.x;
+    if (p >= s.n) return;
+    const int c = s.cell[p];
+    const int b = s.cstart[c], m = s.cstart[c + 1] - b;
+    int rank = 0;
+    for (int k = 0; k < m; k += 4) {  // four members per round, loads first
+        const int o0 = s.order[b + k];
+        const int o1 = s.order[b + min(k + 1, m - 1)];
+        const int o2 = s.order[b + min(k + 2, m - 1)];
+        const int o3 = s.order[b + min(k + 3, m - 1)];
+        rank += (o0 < p) + (k + 1 < m && o1 < p) + (k + 2 < m && o2 < p) + (k + 3 < m && o3 < p);
+    }
+    const int q = b + rank;
+    const double4 x = s.pos[p];
+    const double wx = wrap_box(x.x, s.box), wy = wrap_box(x.y, s.box), wz = wrap_box(x.z, s.box);
+    s.tpos[q] = make_double4(wx, wy, wz, 0.0);
+    s.tposf[q] = make_float4((float)wx, (float)wy, (float)wz, 0.f);
+    s.tvel[q] = s.vel[p];
+    s.tid[q] = s.id[p];
+    if (s.pot == 1) {
+        s.tquat[q] = s.quat[p];
+        s.tangm[q] = s.angm[p];
     }
 }
 
@@ -506,7 +524,6 @@ __device__ __forceinline__ void b_tile_region(const Sys& s, int t) {
         s.tile_nchunk[t] = nchk;
         s.tile_row0[t] = r0;
         s.tile_nseg[t] = nseg;
-        atomicAdd(&s.ctrl->staged, 1);
     }
 }
 
@@ -516,7 +533,7 @@ __device__ __forceinline__ void b_sort_tiles(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     const int ns = sort_blocks(s);
     if (bid < ns) {
-        b_cell_sort(s, bid, ns);
+        b_cell_sort(s, bid);
     } else {
         const int t = (bid - ns) * (kBlock / kWave) + threadIdx.x / kWave;
         if (t < s.ntiles) b_tile_region(s, t);
@@ -614,25 +631,41 @@ __device__ __forceinline__ void region_finish(const Sys& s, const double4* src, 
 
 // ---------------------------------------------------------------------------
 // Verlet-list build: one lane per particle, one wavefront per tile (four
-// tiles per workgroup).  The lane walks its particle's 27 neighbour cells as
-// runs of consecutive slots (one or two per row of cells) in FP64 from the
-// reorder buffer and appends every j != i with r_ij^2 < r_v^2 to its list, so
-// the list order (cell order, then slot) is fixed.  A staged tile takes each
-// run in its periodic image and stores entries that index the tile's region;
-// the others store slots with the minimum-image code.  The build also moves
+// tiles per workgroup).  Each lane appends every j != i with r_ij^2 < r_v^2
+// from its 27 neighbour cells to its list, in a fixed order.  For a staged
+// tile the wavefront walks the tile's region (the union of its particles'
+// neighbourhoods) in FP32 with FP64 deciding inside the rounding band, and
+// entries index the region; otherwise every lane gathers its own cells in
+// FP64 and stores slots with the minimum-image code.  The build also moves
 // the particle records from the reorder buffer back into the state and
 // stores the build reference positions; per-tile totals of the half-list
 // lengths (entries with j > i) feed the half-list offsets.
 // ---------------------------------------------------------------------------
 
 // Exclusive scan of the per-tile half-list totals into tile offsets by one
-// workgroup (the last of the list build); records |E| and the build count.
+// workgroup (the last of the list build); records |E|, the longest list, the
+// staged tiles and the build count.
 __device__ __forceinline__ void scan_tiles(const Sys& s) {
     const long long cap = s.max_half;
-    const long long tot = block_scan(s.bsum, s.ntiles, [&](int k, long long run, int) {
-        s.bsum[k] = (int)(run < cap ? run : cap);
-    });
+    const long long tot = block_scan<16>(
+        s.ntiles, [&](int k) { return coh_load(&s.bsum[k]); },
+        [&](int k, long long run, int) { s.bsum[k] = (int)(run < cap ? run : cap); });
+    __shared__ int rmax[kBlock / kWave], rst[kBlock / kWave];
+    int mx = 0, st = 0;
+    for (int t = threadIdx.x; t < s.ntiles; t += kBlock) {
+        mx = max(mx, coh_load(&s.tmax[t]));
+        st += s.tile_nseg[t] >= 0;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        mx = max(mx, __shfl_xor(mx, off));
+        st += __shfl_xor(st, off);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) rmax[threadIdx.x / kWave] = mx, rst[threadIdx.x / kWave] = st;
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / kWave; w++) mx = max(mx, rmax[w]), st += rst[w];
+        s.ctrl->max_count = mx;
+        s.ctrl->staged = st;
         s.ctrl->npairs = tot < cap ? tot : cap;
         if (tot > cap) atomicOr(&s.ctrl->overflow, 1);
         s.ctrl->rebuilds += 1;
@@ -641,17 +674,31 @@ __device__ __forceinline__ void scan_tiles(const Sys& s) {
     }
 }
 
+// Pointer into the constant address space: the data does not change while
+// the kernel runs, so wavefront-uniform loads through it go to scalar
+// registers (one load for the wavefront instead of one per lane).
+typedef float cf4 __attribute__((ext_vector_type(4)));
+typedef double cd4 __attribute__((ext_vector_type(4)));
+typedef int ci4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ const __attribute__((address_space(4))) cf4* as_const(const float4* p) {
+    return (const __attribute__((address_space(4))) cf4*)p;
+}
+__device__ __forceinline__ const __attribute__((address_space(4))) cd4* as_const(const double4* p) {
+    return (const __attribute__((address_space(4))) cd4*)p;
+}
+__device__ __forceinline__ const __attribute__((address_space(4))) ci4* as_const(const int4* p) {
+    return (const __attribute__((address_space(4))) ci4*)p;
+}
+
 __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int tile = bid * (kBlock / kWave) + (int)threadIdx.x / kWave;  // wavefront-uniform
-    const int i = bid * kBlock + threadIdx.x;  // = tile * kTile + lane
+    const int tile = bid * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)threadIdx.x / kWave);
+    const int i = tile * kTile + lane;
     const bool act = i < s.n;
     const int ii = act ? i : s.n - 1;
     const bool tact = tile < s.ntiles;
     const int nseg = tact ? s.tile_nseg[tile] : -1;
-    const int row0 = nseg >= 0 ? s.tile_row0[tile] : 0;
-    const int4* seg = s.tile_seg + (size_t)(tact ? tile : 0) * kSegMax;
     const double4 xi = s.tpos[ii];
     if (act) {
         s.pos[i] = xi;
@@ -667,8 +714,6 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     const int cx = cell_coord(xi.x, s.cell_inv, nc);
     const int cy = cell_coord(xi.y, s.cell_inv, nc);
     const int cz = cell_coord(xi.z, s.cell_inv, nc);
-    const int span = nc >= 3 ? 3 : nc;  // distinct cells per dimension
-    const int lo = nc >= 3 ? -1 : 0;
     int4* wrow = (int4*)list_row_w(s, ii);  // the particle's current row of four entries
     const int cap = s.cap;
     const double rv2 = s.rv2;
@@ -689,84 +734,136 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
         }
         count++;
     };
-    for (int dz = 0; dz < span; dz++) {
-        int az = cz + lo + dz;
-        const int wz = az < 0 ? 0 : (az >= nc ? 2 : 1);  // image of the cell row
-        az = az < 0 ? az + nc : (az >= nc ? az - nc : az);
-        for (int dy = 0; dy < span; dy++) {
-            int ay = cy + lo + dy;
-            const int wy = ay < 0 ? 0 : (ay >= nc ? 2 : 1);
-            ay = ay < 0 ? ay + nc : (ay >= nc ? ay - nc : ay);
-            // The neighbour cells of this row in list order (dx ascending) as
-            // runs of consecutive cells, i.e. of consecutive slots: one run
-            // (cx - 1 .. cx + 1), or two where the row wraps the box; for
-            // nc < 3 every distinct cell on its own.
-            int a0, b0, w0, a1 = 0, b1 = 0, w1 = 1, nr;
-            if (nc >= 3) {
-                if (cx == 0) {
-                    a0 = b0 = nc - 1, w0 = 0, a1 = 0, b1 = 1, nr = 2;
-                } else if (cx == nc - 1) {
-                    a0 = nc - 2, b0 = nc - 1, w0 = 1, a1 = b1 = 0, w1 = 2, nr = 2;
-                } else {
-                    a0 = cx - 1, b0 = cx + 1, w0 = 1, nr = 1;
-                }
-            } else {
-                a0 = b0 = cx, w0 = 1, nr = nc;
-                if (nc == 2) a1 = b1 = 1 - cx, w1 = cx == 1 ? 2 : 1;
-            }
-            const int rowbase = (az * nc + ay) * nc;
-            for (int run = 0; run < nr; run++) {
-                const int xa = run ? a1 : a0, xb = run ? b1 : b0, wx = run ? w1 : w0;
-                const int cb = act ? s.cstart[rowbase + xa] : 0;
-                const int ce = act ? s.cstart[rowbase + xb + 1] : 0;
-                if (cb >= ce) continue;
-                const int code = wx | wy << 2 | wz << 4;
-                if (nseg >= 0) {
-                    // Staged tile: the entry indexes the tile's region, found
-                    // in the two fixed segment slots of (home row, dz, dy).
-                    // Candidates are taken in the run's periodic image, i.e.
-                    // against x_i minus the image shift.
-                    const int hr = cz * nc + cy - row0;
-                    const int4* sg = seg + ((hr * 3 + dz) * 3 + dy) * 2;
-                    const int base = (hr == 0 || hr == 1) ? tile_lds_base(sg, 2, cb, code) : -1;
-                    if (base < 0) atomicOr(&s.ctrl->overflow, 2);  // region misses a cell
-                    const double sx = xi.x - (double)(wx - 1) * s.box;
-                    const double sy = xi.y - (double)(wy - 1) * s.box;
-                    const double sz = xi.z - (double)(wz - 1) * s.box;
-                    const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
-                    const int eoff = (max(base, 0) - cb) + (code << kSlotBits);
-                    // The test runs in FP32 on the rounded copy of the records;
-                    // where its result lies within the band around r_v^2 that
-                    // bounds its rounding error, FP64 decides, so the list is
-                    // the one the FP64 test gives.
-                    auto consider = [&](int j, const float4& pf) {
-                        const float ex = pf.x - fx, ey = pf.y - fy, ez = pf.z - fz;
-                        const float r2 = ex * ex + ey * ey + ez * ez;
-                        bool in = r2 < s.rv2_lo;
-                        if (r2 >= s.rv2_lo && r2 < s.rv2_hi) {
-                            const double4 pj = s.tpos[j];
-                            const double dx = pj.x - sx, dy = pj.y - sy, dz = pj.z - sz;
-                            in = dx * dx + dy * dy + dz * dz < rv2;
-                        }
-                        if (j < ce && j != i && in) append(j, eoff + j);
-                    };
-                    // Four candidates per round; the next round's loads are
-                    // issued before this round is tested, so that they are in
-                    // flight meanwhile (reads past the run's end land in the
-                    // copy or its spare records and are not used).
-                    const float4* pr = s.tposf + cb;
-                    float4 q0 = pr[0], q1 = pr[1], q2 = pr[2], q3 = pr[3];
-                    for (int j0 = cb; j0 < ce; j0 += 4) {
-                        const float4 p0 = q0, p1 = q1, p2 = q2, p3 = q3;
-                        pr += 4;
-                        q0 = pr[0], q1 = pr[1], q2 = pr[2], q3 = pr[3];
-                        consider(j0 + 0, p0);
-                        consider(j0 + 1, p1);
-                        consider(j0 + 2, p2);
-                        consider(j0 + 3, p3);
+    if (nseg >= 0) {
+        // Staged tile: the wavefront walks the tile's region segment by
+        // segment, in list order (home row, dz, dy, then the two slots of a
+        // row that wraps the box), every lane testing the same candidate, so
+        // the records come through scalar loads.  A segment covers the home
+        // cells' x-range plus one cell either side, so it holds each lane's
+        // three cells of that row; cells further out are beyond r_v.
+        const int hr = cz * nc + cy - s.tile_row0[tile];  // the lane's home row in the tile
+        const auto* sg = as_const(s.tile_seg + (size_t)tile * kSegMax);
+        const auto* cp = as_const(s.tposf);
+        const auto* cp64 = as_const(s.tpos);
+        const float nlo = -s.rv2_lo;
+        const unsigned wbits = __float_as_uint(s.rv2_band);
+        for (int h = 0; h < 2; h++) {
+            const bool inh = act && hr == h;
+            if (!__any(inh)) continue;
+            for (int q = 0; q < 18; q++) {
+                const ci4 g = sg[h * 18 + q];
+                if (g.x >= g.y) continue;
+                // x_i in the segment's periodic image
+                const double sx = xi.x - (double)((g.w & 3) - 1) * s.box;
+                const double sy = xi.y - (double)(((g.w >> 2) & 3) - 1) * s.box;
+                const double sz = xi.z - (double)(((g.w >> 4) & 3) - 1) * s.box;
+                const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
+                const int eoff = g.z - g.x + (g.w << kSlotBits);
+                // The test runs in FP32 on the rounded copy of the records,
+                // as t = |x_j - x_i|^2 - lo: t < 0 is in; t >= w (lo + w is
+                // the band's top) is out; a candidate with t in [0, w) is
+                // decided in FP64, so the list is the one the FP64 test gives.
+                auto tbits = [&](const cf4& pf) {
+                    const float ex = pf.x - fx, ey = pf.y - fy, ez = pf.z - fz;
+                    return __float_as_uint(
+                        __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, __builtin_fmaf(ex, ex, nlo))));
+                };
+                // Hits collect as bits j - c0 of (ma, mb) and are appended
+                // per part of at most 128 candidates.
+                auto flush = [&](int c0, int c1, unsigned long long ma, unsigned long long mb) {
+                    const int nv = c1 - c0;
+                    if (nv < 64) ma &= (1ull << nv) - 1;
+                    mb &= nv >= 128 ? ~0ull : (nv > 64 ? (1ull << (nv - 64)) - 1 : 0ull);
+                    const int bi = i - c0;  // the particle itself
+                    if ((unsigned)bi < 64u) ma &= ~(1ull << bi);
+                    else if ((unsigned)(bi - 64) < 64u) mb &= ~(1ull << (bi - 64));
+                    if (!inh) ma = mb = 0;
+                    while (ma | mb) {
+                        const bool low = ma != 0;
+                        const unsigned long long x = low ? ma : mb;
+                        const int j = c0 + __builtin_ctzll(x) + (low ? 0 : 64);
+                        const unsigned long long x2 = x & (x - 1);
+                        ma = low ? x2 : ma;
+                        mb = low ? mb : x2;
+                        append(j, eoff + j);
                     }
+                };
+                // Eight candidates per round (reads past the segment's end
+                // land in the copy or its spare records; their bits are
+                // cleared); the next round's records are loaded before this
+                // round is tested.
+                cf4 qn[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) qn[u] = cp[g.x + u];
+                unsigned long long ma = 0, mb = 0;
+                int c0 = g.x;
+                for (int j0 = g.x; j0 < g.y; j0 += 8) {
+                    cf4 pv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) pv[u] = qn[u];
+#pragma unroll
+                    for (int u = 0; u < 8; u++) qn[u] = cp[j0 + 8 + u];
+                    unsigned m8 = 0, tmin = ~0u;
+#pragma unroll
+                    for (int u = 0; u < 8; u++) {
+                        const unsigned tb = tbits(pv[u]);
+                        tmin = min(tmin, tb);
+                        m8 |= (tb >> 31) << u;
+                    }
+                    if (tmin < wbits) {  // rare: FP64 decides the candidates in the band
+#pragma unroll
+                        for (int u = 0; u < 8; u++) {
+                            const int j = j0 + u;
+                            if (tbits(pv[u]) < wbits && j < g.y) {
+                                const cd4 pj = cp64[j];
+                                const double dx = pj.x - sx, dy = pj.y - sy, dz = pj.z - sz;
+                                if (dx * dx + dy * dy + dz * dz < rv2) m8 |= 1u << u;
+                            }
+                        }
+                    }
+                    const int o = j0 - c0;
+                    const unsigned long long w = (unsigned long long)m8 << (o & 63);
+                    ma |= o < 64 ? w : 0ull;
+                    mb |= o < 64 ? 0ull : w;
+                    if (o + 8 == 128 && j0 + 8 < g.y) {  // a part of 128 is full
+                        flush(c0, c0 + 128, ma, mb);
+                        ma = mb = 0;
+                        c0 = j0 + 8;
+                    }
+                }
+                flush(c0, g.y, ma, mb);
+            }
+        }
+        if (act && (unsigned)hr > 1u) atomicOr(&s.ctrl->overflow, 2);  // region misses the particle
+    } else {
+        // Global gathers: every lane walks its own 27 cells as runs of
+        // consecutive slots (one or two per row of cells) and stores slot
+        // entries with the minimum-image code.
+        const int span = nc >= 3 ? 3 : nc;  // distinct cells per dimension
+        const int lo = nc >= 3 ? -1 : 0;
+        for (int dz = 0; dz < span; dz++) {
+            int az = cz + lo + dz;
+            az = az < 0 ? az + nc : (az >= nc ? az - nc : az);
+            for (int dy = 0; dy < span; dy++) {
+                int ay = cy + lo + dy;
+                ay = ay < 0 ? ay + nc : (ay >= nc ? ay - nc : ay);
+                // The neighbour cells of this row in list order (dx ascending)
+                // as runs of consecutive cells: one run (cx - 1 .. cx + 1), or
+                // two where the row wraps the box; for nc < 3 every distinct
+                // cell on its own.
+                int a0, b0, a1 = 0, b1 = 0, nr;
+                if (nc >= 3) {
+                    if (cx == 0) a0 = b0 = nc - 1, a1 = 0, b1 = 1, nr = 2;
+                    else if (cx == nc - 1) a0 = nc - 2, b0 = nc - 1, a1 = b1 = 0, nr = 2;
+                    else a0 = cx - 1, b0 = cx + 1, nr = 1;
                 } else {
-                    // Global gathers: slot entries with the minimum-image code.
+                    a0 = b0 = cx, nr = nc;
+                    if (nc == 2) a1 = b1 = 1 - cx;
+                }
+                const int rowbase = (az * nc + ay) * nc;
+                for (int run = 0; run < nr; run++) {
+                    const int cb = act ? s.cstart[rowbase + (run ? a1 : a0)] : 0;
+                    const int ce = act ? s.cstart[rowbase + (run ? b1 : b0) + 1] : 0;
                     auto consider = [&](int j, const double4& pj) {
                         const double ex = pj.x - xi.x, ey = pj.y - xi.y, ez = pj.z - xi.z;
                         const double ddx = wrap_delta(ex, s.box, s.inv_box);
@@ -800,14 +897,18 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
         mx = max(mx, __shfl_xor(mx, off));
         hs += __shfl_xor(hs, off);
     }
-    if (lane == 0 && tact) {
-        atomicMax(&s.ctrl->max_count, mx);
-        s.bsum[tile] = hs;
+    if (lane == 0 && tact) {  // read by the last workgroup
+        coh_store(&s.tmax[tile], mx);
+        coh_store(&s.bsum[tile], hs);
     }
-    if (last_block(&s.ctrl->done_build, nb)) scan_tiles(s);
+    if (last_block(s.sync + kSyncBuild * kSyncInts, bid, nb)) scan_tiles(s);
 }
 
-__global__ __launch_bounds__(kBlock) void k_build(Sys s) { b_build(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+// At most 128 VGPRs: four wavefronts per SIMD, one full wave of the chip for
+// every 1024 tiles.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_build(Sys s) {
+    b_build(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
 
 
 // Half list (edge and Newton passes), filled on demand after a build: one
@@ -886,7 +987,7 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
     }
     // the last workgroup marks the list current (every workgroup has passed
     // its check of the flag by then)
-    if (last_block(&s.ctrl->done_half, nb) && threadIdx.x == 0) s.ctrl->half_stale = 0;
+    if (last_block(s.sync + kSyncHalf * kSyncInts, bid, nb) && threadIdx.x == 0) s.ctrl->half_stale = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_half_fill(Sys s) { b_half_fill(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
@@ -1813,7 +1914,7 @@ hipError_t launch_set_rebuild(const Sys& s, hipStream_t st) {
 }
 
 hipError_t launch_clear_ctrl(const Sys& s, hipStream_t st) {
-    hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(1), 0, st, s.ctrl);
+    hipLaunchKernelGGL(k_clear_ctrl, dim3(1), dim3(kBlock), 0, st, s.ctrl, s.sync);
     return hipGetLastError();
 }
 
@@ -2014,7 +2115,7 @@ __global__ __launch_bounds__(kBlock) void kb_sort_tiles(BatchDev b, int step) {
     });
 }
 
-__global__ __launch_bounds__(kBlock) void kb_build(BatchDev b, int step) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kb_build(BatchDev b, int step) {
     batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) { b_build(s, lb, s.nblk); });
 }
 
