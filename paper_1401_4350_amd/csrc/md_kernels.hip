@@ -66,6 +66,15 @@ __device__ __forceinline__ int* list_row_w(const Sys& s, int i) {
     return s.nbr + (((size_t)(i / kTile) * s.mcap) * kTile + (i % kTile)) * 4;
 }
 __device__ __forceinline__ size_t list_off(int k) { return (size_t)(k >> 2) * (kTile * 4) + (k & 3); }
+// A staged tile's entries are 16-bit indices into its region (the region
+// copy carries the periodic image), eight per 16-byte row: entry k of
+// particle i at 16-bit word ((t * mcap + k / 8) * kTile + p) * 8 + k % 8 of
+// the same block, so the tile uses ceil(cap / 8) of its rows and a lane's
+// 32-bit load brings two entries.
+__device__ __forceinline__ const uint16_t* list_row16(const Sys& s, int i) {
+    return reinterpret_cast<const uint16_t*>(list_row(s, i));
+}
+__device__ __forceinline__ size_t list_off16(int k) { return (size_t)(k >> 3) * (kTile * 8) + (k & 7); }
 
 __device__ __forceinline__ double image(int e, int axis, double box) {
     int c = (e >> (kSlotBits + 2 * axis)) & 3;
@@ -719,6 +728,7 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     const double rv2 = s.rv2;
     int count = 0, half = 0;
     int e0 = 0, e1 = 0, e2 = 0;  // entries of the current row not yet written
+    int w0 = 0, w1 = 0, w2 = 0, w3 = 0;  // staged tile: the current row of eight 16-bit entries
     // Appends entry `ent` for partner j; a row of four goes out in one store.
     auto append = [&](int j, int ent) {
         if (count < cap) {
@@ -730,6 +740,24 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
             e0 = sl == 0 ? ent : e0;
             e1 = sl == 1 ? ent : e1;
             e2 = sl == 2 ? ent : e2;
+            half += j > i;
+        }
+        count++;
+    };
+    // Staged tile: appends region index `reg` for partner j (16-bit entries).
+    auto append16 = [&](int j, int reg) {
+        if (count < cap) {
+            const int sl = count & 7, wd = sl >> 1;
+            const bool hi = sl & 1;
+            const int v = hi ? reg << 16 : reg;
+            w0 = wd == 0 ? (hi ? w0 | v : v) : w0;
+            w1 = wd == 1 ? (hi ? w1 | v : v) : w1;
+            w2 = wd == 2 ? (hi ? w2 | v : v) : w2;
+            w3 = wd == 3 ? (hi ? w3 | v : v) : w3;
+            if (sl == 7) {
+                *wrow = make_int4(w0, w1, w2, w3);
+                wrow += kTile;
+            }
             half += j > i;
         }
         count++;
@@ -758,7 +786,7 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                 const double sy = xi.y - (double)(((g.w >> 2) & 3) - 1) * s.box;
                 const double sz = xi.z - (double)(((g.w >> 4) & 3) - 1) * s.box;
                 const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
-                const int eoff = g.z - g.x + (g.w << kSlotBits);
+                const int roff = g.z - g.x;  // region index of slot j: roff + j
                 // The test runs in FP32 on the rounded copy of the records,
                 // as t = |x_j - x_i|^2 - lo: t < 0 is in; t >= w (lo + w is
                 // the band's top) is out; a candidate with t in [0, w) is
@@ -785,7 +813,7 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                         const unsigned long long x2 = x & (x - 1);
                         ma = low ? x2 : ma;
                         mb = low ? mb : x2;
-                        append(j, eoff + j);
+                        append16(j, roff + j);
                     }
                 };
                 // Eight candidates per round (reads past the segment's end
@@ -885,7 +913,8 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
             }
         }
     }
-    if (act && (min(count, cap) & 3)) *wrow = make_int4(e0, e1, e2, 0);  // last, partial row
+    if (act && (min(count, cap) & (nseg >= 0 ? 7 : 3)))  // last, partial row
+        *wrow = nseg >= 0 ? make_int4(w0, w1, w2, w3) : make_int4(e0, e1, e2, 0);
     if (act) {
         s.ncount[i] = count < cap ? count : cap;
         s.hcount[i] = half;
@@ -935,7 +964,7 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
         const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
         for (int c = threadIdx.x / kWave; c < nchk; c += kBlock / kWave) {
             int4 d = chk[c];
-            if (lane < d.y - d.x) map[d.z + lane] = d.x + lane;
+            if (lane < d.y - d.x) map[d.z + lane] = (d.x + lane) | d.w << kSlotBits;
         }
     }
     if (threadIdx.x < kTile) {
@@ -966,21 +995,28 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
     }
     const int cnt = act ? s.ncount[i] : 0;
     const int* row = list_row(s, act ? i : 0);
+    const uint16_t* row16 = list_row16(s, act ? i : 0);
     int mine = cnt > q ? (cnt - q + TPP - 1) / TPP : 0;
     int mmax = mine;
     for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
     long long k = start;
     for (int m = 0; m < mmax; m++) {
         bool ok = m < mine;
-        int ent = ok ? row[list_off(q + m * TPP)] : 0;
-        const int reg = entry_slot(ent);
-        int j = reg;
-        if (ok && nseg >= 0) j = map[reg];  // LDS index -> slot
+        int ent = 0, reg = 0;
+        if (ok) {
+            if (nseg >= 0) {  // region index -> slot with image
+                reg = row16[list_off16(q + m * TPP)];
+                ent = map[reg];
+            } else {
+                ent = row[list_off(q + m * TPP)];
+            }
+        }
+        const int j = entry_slot(ent);
         const bool keep = ok && j > i;
         const unsigned grp = (unsigned)(__ballot(keep) >> gshift) & ((1u << TPP) - 1);
         const long long kk = k + __builtin_popcount(grp & ((1u << q) - 1));
         if (keep && kk < end) {
-            s.hj[kk] = j | (ent & ~kSlotMask);
+            s.hj[kk] = ent;
             if (nseg >= 0) s.hr[kk] = (uint16_t)reg;  // the edge pass accumulates by region
         }
         k += __builtin_popcount(grp);
@@ -1153,8 +1189,9 @@ __device__ __forceinline__ void lj_lds_term(const Sys& s, const double* lds, int
 }
 
 // One workgroup per tile of kTile particles, TPP = kBlock / kTile lanes per
-// particle (lane q of particle i takes entries q, q + TPP, ...).  A staged
-// tile requests the lane's first kPrefetch list entries, copies its region
+// particle (in a staged tile lane q of particle i takes entries 2q, 2q + 1,
+// 2q + 8, 2q + 9, ...; otherwise q, q + TPP, ...).  A staged tile requests the
+// lane's first kPrefetch list entries, copies its region
 // into LDS meanwhile, then evaluates the entries from LDS in groups of four
 // under a wave-uniform trip count (entries past the list end point at the
 // padding slot).  Unstaged tiles gather from global memory.
@@ -1181,8 +1218,9 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     double e = 0, w = 0;
     if (nseg >= 0) {
         constexpr int E = kPrefetch;
-        const int* nb = list_row(s, ii);
-        int mine = cnt > q ? (cnt - q + TPP - 1) / TPP : 0;  // entries of this lane
+        // lane entry n is list entry 8 (n / 2) + 2 q + n % 2 (16-bit entries,
+        // two per 32-bit word, four words per row of a particle)
+        const int mine = 2 * (cnt >> 3) + min(max((cnt & 7) - 2 * q, 0), 2);  // entries of this lane
         int mmax = mine;
         for (int off = kWave / 2; off > 0; off >>= 1) mmax = max(mmax, __shfl_xor(mmax, off));
         mmax = __builtin_amdgcn_readfirstlane(mmax);
@@ -1191,24 +1229,25 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
         const int nchk = s.tile_nchunk[tile];
         RegionBatch rb;
         region_issue(s, s.pos, tile, nchk, wv, rb);
-        // Entry row m of this lane sits at int offset 256 m + threadIdx.x of
-        // the tile's rows (list_off with four lanes per particle), so a block
-        // of E rows is one lane base plus constant offsets.  Every lane issues
-        // all E loads (the list allocation has kListPadRows spare rows after
-        // the last tile), so no load sits behind a branch; entries past the
-        // lane's list end become the padding slot.
-        static_assert(TPP == 4 && kTile * TPP == kBlock, "entry offset 256 m + tid");
-        static_assert(E <= kListPadRows, "prefetch beyond the spare rows");
+        // The word of lane entries n, n + 1 (n even) in row n / 2 sits at
+        // int offset 256 (n / 2) + threadIdx.x of the tile's rows, so a block
+        // of E entries is one lane base plus constant offsets.  Every lane
+        // issues all E / 2 loads (the list allocation has kListPadRows spare
+        // rows after the last tile), so no load sits behind a branch; entries
+        // past the lane's list end become the padding slot.
+        static_assert(TPP == 4 && kTile * TPP == kBlock, "word offset 256 m + tid");
+        static_assert(E % 2 == 0 && E / 2 <= kListPadRows, "prefetch beyond the spare rows");
         const int* lane_rows = s.nbr + (size_t)tile * s.mcap * (kTile * 4) + threadIdx.x;
-        auto load_block = [&](int m0, int (&en)[E]) {
-            const int* bp = lane_rows + (size_t)m0 * (kTile * 4);
+        auto load_block = [&](int n0, int (&en)[E]) {
+            const int* bp = lane_rows + (size_t)(n0 >> 1) * (kTile * 4);
 #pragma unroll
-            for (int m = 0; m < E; m++) {
-                int v = __builtin_nontemporal_load(bp + m * (kTile * 4));
-                // past the end: all slot bits set, clamped to the padding slot;
-                // the value depends on the load either way, so the compiler
-                // cannot move the load under a branch
-                en[m] = min(entry_slot(v) | (m0 + m < mine ? 0 : kSlotMask), cap);
+            for (int m = 0; m < E / 2; m++) {
+                const int v = __builtin_nontemporal_load(bp + m * (kTile * 4));
+                // past the end: all index bits set, clamped to the padding
+                // slot; the value depends on the load either way, so the
+                // compiler cannot move the load under a branch
+                en[2 * m] = min((v & 0xffff) | (n0 + 2 * m < mine ? 0 : 0xffff), cap);
+                en[2 * m + 1] = min((int)((unsigned)v >> 16) | (n0 + 2 * m + 1 < mine ? 0 : 0xffff), cap);
             }
         };
         auto eval_block = [&](int m0, const int (&en)[E]) {
@@ -1279,11 +1318,10 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     }
 }
 
-// The staged region limits the pass to at most four workgroups (four waves
-// per SIMD) per CU, so the register allocator may use that budget to keep the
-// list prefetch in flight instead of aiming at more waves.
+// The staged region limits the pass to four workgroups (four waves per SIMD)
+// per CU; at most 128 VGPRs keep all four resident.
 template <int PREC, int TPP, bool KICK, bool ENERGY, bool DRIFT = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_vertex_lj(Sys s) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_vertex_lj(Sys s) {
     b_vertex_lj<PREC, TPP, KICK, ENERGY, DRIFT>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
