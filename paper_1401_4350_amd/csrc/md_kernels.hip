@@ -1155,13 +1155,12 @@ constexpr int kPrefetch = MD_VERTEX_PREFETCH;  // list entries held in registers
 // image.  The cut-off selects a 0/1 factor, so every lane runs the same
 // instruction stream.
 template <int PREC, bool ENERGY>
-__device__ __forceinline__ void lj_lds_term(const Sys& s, const double* lds, int k,
+__device__ __forceinline__ void lj_pos_term(const Sys& s, double px, double py, double pz,
                                             const double4& xi, Acc3<PREC>& f, double& e,
                                             double& w) {
-    const double* p = lds + 3 * k;
-    double dx = p[0] - xi.x;
-    double dy = p[1] - xi.y;
-    double dz = p[2] - xi.z;
+    double dx = px - xi.x;
+    double dy = py - xi.y;
+    double dz = pz - xi.z;
     double r2 = dx * dx + dy * dy + dz * dz;
     bool in = r2 < s.rc2;
     if (PREC == 0) {
@@ -1250,13 +1249,22 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
                 en[2 * m + 1] = min((int)((unsigned)v >> 16) | (n0 + 2 * m + 1 < mine ? 0 : 0xffff), cap);
             }
         };
+        // groups of four: the four records are read from LDS before the
+        // first is used, so their latencies overlap
         auto eval_block = [&](int m0, const int (&en)[E]) {
 #pragma unroll
             for (int m = 0; m < E; m += 4) {
                 if (m0 + m < mmax) {
+                    double px[4], py[4], pz[4];
 #pragma unroll
-                    for (int u = 0; u < 4; u++)
-                        lj_lds_term<PREC, ENERGY>(s, lds3, en[m + u], xi, f, e, w);
+                    for (int u = 0; u < 4; u++) {
+                        const double* p = lds3 + 3 * en[m + u];
+                        px[u] = p[0];
+                        py[u] = p[1];
+                        pz[u] = p[2];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++) lj_pos_term<PREC, ENERGY>(s, px[u], py[u], pz[u], xi, f, e, w);
                 }
             }
         };
