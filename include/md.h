@@ -23,6 +23,12 @@
  *                   in the paper), or, with newton_m = 0, into a per-workgroup
  *                   LDS accumulator over the tile's neighbour region that is
  *                   added to the forces once per workgroup.  LJ only.
+ *   MD_MODE_EDGE_DET the edge approach made deterministic as the Methods
+ *                   section describes as its alternative to atomics: one
+ *                   thread per half-list entry stores the pair's result per
+ *                   edge, and one thread per particle then sums the stored
+ *                   results of its edges in the fixed order of its list
+ *                   (needs md_params.edge_store = 1).  Bitwise reproducible.
  *
  * Both read Verlet lists of radius r_v = r_c + r_s built with a cell algorithm
  * (Methods section), and are followed by an FP64 velocity-Verlet update
@@ -68,7 +74,7 @@ typedef enum {
 } md_status;
 
 typedef enum { MD_POT_LJ = 0, MD_POT_PATCHY = 1 } md_potential;
-typedef enum { MD_MODE_VERTEX = 0, MD_MODE_EDGE = 1, MD_MODE_NEWTON = 2 } md_mode;
+typedef enum { MD_MODE_VERTEX = 0, MD_MODE_EDGE = 1, MD_MODE_NEWTON = 2, MD_MODE_EDGE_DET = 3 } md_mode;
 
 /* Arithmetic of the pair forces.  Positions, velocities and the integrator are
  * FP64 in every variant (Methods section, mixed precision). */
@@ -97,7 +103,9 @@ typedef struct {
     double inertia;        /* isotropic moment of inertia > 0                        */
     /* MD_MODE_NEWTON only */
     int32_t newton_m;      /* replicated force arrays, 1 .. 64; 0: LDS accumulation  */
-    int32_t reserved;      /* must be 0                                              */
+    int32_t edge_store;    /* 1: workspace for MD_MODE_EDGE_DET (8 B x 3 (LJ) or 9     */
+                           /* (patchy) per half-list entry, 4 B per full-list slot);  */
+                           /* 0: none.  Half-list capacity below 2^31 entries          */
 } md_params;
 
 typedef struct {

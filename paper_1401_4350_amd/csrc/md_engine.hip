@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -29,7 +30,7 @@ struct Layout {
     uint64_t pos, vel, frc, quat, angm, trq, id;
     // workspace offsets
     uint64_t pos_alt, xbuild, tpos, tposf, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
-        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, tmax, sync, epart, wpart, kpart, red, ctrl, tile_seg,
+        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, tmax, sync, ef, eidx, epart, wpart, kpart, red, ctrl, tile_seg,
         tile_nseg, tile_chunk, tile_nchunk, tile_row0;
     int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
     long long max_half = 0;
@@ -60,7 +61,11 @@ md_status validate(const md_params* p) {
             !fin(p->patch_rcut))
             return MD_ERR_INVALID_ARG;
     }
-    if (p->newton_m < 0 || p->newton_m > 64 || p->reserved != 0) return MD_ERR_INVALID_ARG;
+    if (p->newton_m < 0 || p->newton_m > 64 || (p->edge_store != 0 && p->edge_store != 1))
+        return MD_ERR_INVALID_ARG;
+    // edge indices of the deterministic edge mode are 31-bit
+    if (p->edge_store && (long long)p->n * p->max_neighbors / 2 + 4096 >= (long long)INT_MAX)
+        return MD_ERR_INVALID_ARG;
     double rv = p->rcut + p->skin;
     if (!(p->box > 2.0 * rv)) return MD_ERR_BOX_TOO_SMALL;
     // 32-bit slot and half-list indices
@@ -149,6 +154,11 @@ Layout layout(const md_params& p) {
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
     L.bsum = take(cur, 4 * (uint64_t)std::max(L.nblk, L.ntiles));  // per-tile half totals
     L.tmax = take(cur, 4 * (uint64_t)L.ntiles);
+    // deterministic edge mode: per-edge results (F, and tau_i, tau_j for
+    // patchy) and an edge index per full-list entry
+    const uint64_t ncomp = p.pot == MD_POT_LJ ? 3 : 9;
+    L.ef = take(cur, p.edge_store ? 8 * ncomp * (uint64_t)L.max_half : 0);
+    L.eidx = take(cur, p.edge_store ? 4 * (uint64_t)L.ntiles * ((p.max_neighbors + 3) / 4) * md::kTile * 4 : 0);
     L.sync = take(cur, 4 * (uint64_t)md::kSyncUses * md::kSyncInts);
     L.tile_seg = take(cur, 16 * (uint64_t)L.ntiles * md::kSegMax);
     L.tile_nseg = take(cur, 4 * (uint64_t)L.ntiles);
@@ -329,6 +339,9 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.chunk_row = (int*)(W + L.chunk_row);
     y.bsum = (int*)(W + L.bsum);
     y.tmax = (int*)(W + L.tmax);
+    y.estore = p->edge_store;
+    y.ef = p->edge_store ? (double*)(W + L.ef) : nullptr;
+    y.eidx = p->edge_store ? (int*)(W + L.eidx) : nullptr;
     y.sync = (int*)(W + L.sync);
     y.ntiles = L.ntiles;
     y.lds_cap = L.lds_cap;
@@ -449,15 +462,24 @@ md_status md_build_neighbors(md_system* s) {
     return MD_OK;
 }
 
-md_status md_forces(md_system* s, int32_t mode) {
-    if (!s) return MD_ERR_INVALID_ARG;
-    if (s->batch) return s->admitted();
-    if (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE && mode != MD_MODE_NEWTON)
+static md_status check_mode(md_system* s, int32_t mode) {
+    if (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE && mode != MD_MODE_NEWTON &&
+        mode != MD_MODE_EDGE_DET)
         return s->fail(MD_ERR_INVALID_ARG, "mode");
     if (mode == MD_MODE_NEWTON && s->p.pot != MD_POT_LJ)
         return s->fail(MD_ERR_INVALID_ARG, "the Newton mode is implemented for LJ only");
+    if (mode == MD_MODE_EDGE_DET && !s->p.edge_store)
+        return s->fail(MD_ERR_INVALID_ARG, "the deterministic edge mode needs edge_store = 1 at md_create");
+    return MD_OK;
+}
+
+md_status md_forces(md_system* s, int32_t mode) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
+    md_status r = check_mode(s, mode);
+    if (r != MD_OK) return r;
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
-    md_status r = s->hip(md::launch_forces(s->sys, mode, s->p.prec, false, s->stream, s->edge_grid),
+    r = s->hip(md::launch_forces(s->sys, mode, s->p.prec, false, s->stream, s->edge_grid),
                          "forces");
     if (r != MD_OK) return r;
     s->forces_valid = true;
@@ -467,10 +489,9 @@ md_status md_forces(md_system* s, int32_t mode) {
 md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     if (!s) return MD_ERR_INVALID_ARG;
     if (s->batch) return s->admitted();
-    if (nsteps < 0 || (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE && mode != MD_MODE_NEWTON))
-        return s->fail(MD_ERR_INVALID_ARG, "nsteps/mode");
-    if (mode == MD_MODE_NEWTON && s->p.pot != MD_POT_LJ)
-        return s->fail(MD_ERR_INVALID_ARG, "the Newton mode is implemented for LJ only");
+    if (nsteps < 0) return s->fail(MD_ERR_INVALID_ARG, "nsteps");
+    md_status rm = check_mode(s, mode);
+    if (rm != MD_OK) return rm;
     if (!s->lists_valid) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
     if (!s->forces_valid) {
         md_status r = md_forces(s, mode);

@@ -36,7 +36,7 @@ struct Ctrl {
     long long npairs;   // half-list entries at the last build (clamped to capacity)
     long long rebuilds; // number of builds
     int half_stale;     // the half list predates the last build (filled on demand)
-    int pad1;
+    int eidx_stale;     // the edge index of the full-list entries predates the half list
     long long pad[2];
 };
 
@@ -49,7 +49,7 @@ struct Ctrl {
 constexpr int kSyncFan = 64;
 constexpr int kSyncStride = 16;
 constexpr int kSyncInts = (kSyncFan + 1) * kSyncStride;
-enum SyncUse { kSyncBin = 0, kSyncBuild, kSyncHalf, kSyncUses };
+enum SyncUse { kSyncBin = 0, kSyncBuild, kSyncHalf, kSyncCol, kSyncUses };
 
 // Pair-potential constants in the arithmetic type of the pair maths.
 template <typename R>
@@ -119,6 +119,12 @@ struct Sys {
     int* chunk_row;  // first row of every 64-pair chunk of the half list
     int* bsum;       // per-block half counts, then offsets
     int* tmax;       // per-tile longest full list of the last build
+    // deterministic edge mode (estore != 0): per-edge results and, for every
+    // full-list entry, its half-list edge (bit 31 set: the particle is the
+    // edge's second member; -1: none), tiled like 32-bit nbr entries
+    int estore;
+    double* ef;      // [ncomp * max_half]: F on the second member, then (patchy) tau_i, tau_j
+    int* eidx;
     int* sync;       // [kSyncUses * kSyncInts] completion counters
     int ntiles;      // ceil(n / kTile)
     int lds_cap;     // region capacity (particles) of a tile staged in LDS

@@ -75,6 +75,11 @@ __device__ __forceinline__ const uint16_t* list_row16(const Sys& s, int i) {
     return reinterpret_cast<const uint16_t*>(list_row(s, i));
 }
 __device__ __forceinline__ size_t list_off16(int k) { return (size_t)(k >> 3) * (kTile * 8) + (k & 7); }
+// Edge index of full-list entry k of particle i (deterministic edge mode):
+// word list_off(k) of eidx_row(s, i), laid out like 32-bit list entries.
+__device__ __forceinline__ int* eidx_row(const Sys& s, int i) {
+    return s.eidx + (((size_t)(i / kTile) * s.mcap) * kTile + (i % kTile)) * 4;
+}
 
 __device__ __forceinline__ double image(int e, int axis, double box) {
     int c = (e >> (kSlotBits + 2 * axis)) & 3;
@@ -679,6 +684,7 @@ __device__ __forceinline__ void scan_tiles(const Sys& s) {
         if (tot > cap) atomicOr(&s.ctrl->overflow, 1);
         s.ctrl->rebuilds += 1;
         s.ctrl->half_stale = 1;
+        s.ctrl->eidx_stale = s.estore;
         s.ctrl->rebuild = 0;  // every workgroup of the build has read it
     }
 }
@@ -1015,6 +1021,9 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
         const bool keep = ok && j > i;
         const unsigned grp = (unsigned)(__ballot(keep) >> gshift) & ((1u << TPP) - 1);
         const long long kk = k + __builtin_popcount(grp & ((1u << q) - 1));
+        // deterministic edge mode: entries with j > i are edge kk of this row
+        // (the others are filled by the column pass)
+        if (s.estore && keep) eidx_row(s, i)[list_off(q + m * TPP)] = kk < end ? (int)kk : -1;
         if (keep && kk < end) {
             s.hj[kk] = ent;
             if (nseg >= 0) s.hr[kk] = (uint16_t)reg;  // the edge pass accumulates by region
@@ -1027,6 +1036,51 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_half_fill(Sys s) { b_half_fill(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+
+// Deterministic edge mode, after the half list: every full-list entry of
+// particle i whose partner j is below i gets the index of edge (j, i) in row
+// j of the half list, found by a walk over that row, with bit 31 set (i is
+// the edge's second member); -1 if the row does not hold it.  One workgroup
+// per tile, four lanes per particle, like the half-list fill.
+__device__ __forceinline__ void b_col_fill(const Sys& s, int bid, int nb) {
+    if (!s.ctrl->eidx_stale) return;
+    extern __shared__ int map[];
+    constexpr int TPP = kTileTpp;
+    const int tile = bid;
+    const int i = tile * kTile + threadIdx.x / TPP;
+    const int q = threadIdx.x % TPP;
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool act = i < s.n;
+    const int nseg = s.tile_nseg[tile];
+    if (nseg >= 0) {
+        const int nchk = s.tile_nchunk[tile];
+        const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
+        for (int c = threadIdx.x / kWave; c < nchk; c += kBlock / kWave) {
+            int4 d = chk[c];
+            if (lane < d.y - d.x) map[d.z + lane] = d.x + lane;
+        }
+    }
+    __syncthreads();
+    const int cnt = act ? s.ncount[i] : 0;
+    const int* row = list_row(s, act ? i : 0);
+    const uint16_t* row16 = list_row16(s, act ? i : 0);
+    int* erow = eidx_row(s, act ? i : 0);
+    for (int kq = q; kq < cnt; kq += TPP) {
+        const int j = nseg >= 0 ? map[row16[list_off16(kq)]] : entry_slot(row[list_off(kq)]);
+        if (j >= i) continue;
+        int v = -1;
+        const int e1 = s.hstart[j + 1];
+        for (int e = s.hstart[j]; e < e1; e++)
+            if (entry_slot(s.hj[e]) == i) {
+                v = e | INT_MIN;
+                break;
+            }
+        erow[list_off(kq)] = v;
+    }
+    if (last_block(s.sync + kSyncCol * kSyncInts, bid, nb) && threadIdx.x == 0) s.ctrl->eidx_stale = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_col_fill(Sys s) { b_col_fill(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
 
 // ---------------------------------------------------------------------------
 // Vertex decomposition: one thread per particle, no atomics.  Each thread
@@ -1426,7 +1480,9 @@ __device__ __forceinline__ double seg_sum(double v, int key, int lane) {
     return v;
 }
 
-template <int POT, int PREC>
+// STORE (deterministic edge mode): no atomics; every edge's results go to
+// the per-edge arrays (zeros included) for the gather pass.
+template <int POT, int PREC, bool STORE = false>
 __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
     using R = typename std::conditional<PREC == 0, double, float>::type;
     const long long npairs = s.ctrl->npairs;
@@ -1493,6 +1549,24 @@ __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
                 }
             }
         }
+        if (STORE) {
+            if (valid) {
+                const size_t H = (size_t)s.max_half;
+                double* ef = s.ef + e;
+                ef[0] = fx;
+                ef[H] = fy;
+                ef[2 * H] = fz;
+                if (POT == 1) {
+                    ef[3 * H] = tix;
+                    ef[4 * H] = tiy;
+                    ef[5 * H] = tiz;
+                    ef[6 * H] = tjx;
+                    ef[7 * H] = tjy;
+                    ef[8 * H] = tjz;
+                }
+            }
+            continue;
+        }
         const bool nz = (fx != 0.0) | (fy != 0.0) | (fz != 0.0) | (tix != 0.0) | (tiy != 0.0) |
                         (tiz != 0.0) | (tjx != 0.0) | (tjy != 0.0) | (tjz != 0.0);
         // j side: only non-zero pairs touch memory
@@ -1537,8 +1611,46 @@ __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
     }
 }
 
-template <int POT, int PREC>
-__global__ __launch_bounds__(kBlock) void k_edge(Sys s) { b_edge<POT, PREC>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+template <int POT, int PREC, bool STORE = false>
+__global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
+    b_edge<POT, PREC, STORE>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Deterministic edge mode, second pass: one thread per particle sums the
+// stored results of its edges in the order of its full list (-F as the
+// edge's first member, +F as its second; tau_i or tau_j), so the forces do
+// not depend on scheduling.  Writes F (and tau) for the closing kick.
+template <int POT>
+__device__ __forceinline__ void b_edge_gather(const Sys& s, int bid, int nb) {
+    const int i = bid * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    const size_t H = (size_t)s.max_half;
+    const int cnt = s.ncount[i];
+    const int* erow = eidx_row(s, i);
+    double fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
+    for (int k = 0; k < cnt; k++) {
+        const int v = erow[list_off(k)];
+        if (v == -1) continue;
+        const size_t e = (size_t)(v & INT_MAX);
+        const bool second = v < 0;
+        const double g = second ? 1.0 : -1.0;
+        fx += g * s.ef[e];
+        fy += g * s.ef[H + e];
+        fz += g * s.ef[2 * H + e];
+        if (POT == 1) {
+            const size_t t0 = second ? 6 * H : 3 * H;
+            tx += s.ef[t0 + e];
+            ty += s.ef[t0 + H + e];
+            tz += s.ef[t0 + 2 * H + e];
+        }
+    }
+    s.frc[i] = make_double4(fx, fy, fz, 0.0);
+    if (POT == 1) s.trq[i] = make_double4(tx, ty, tz, 0.0);
+    if (!isfinite(fx + fy + fz + tx + ty + tz)) atomicOr(&s.ctrl->nonfinite, 1);
+}
+
+template <int POT>
+__global__ __launch_bounds__(kBlock) void k_edge_gather(Sys s) { b_edge_gather<POT>(s, blockIdx.x, gridDim.x); }
 
 // Adds a staged tile's region accumulator (three planes, like the staged
 // positions) to the global forces: one atomic per non-zero component, the
@@ -1981,6 +2093,7 @@ hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists) 
 hipError_t launch_half_fill(const Sys& s, hipStream_t st) {
     size_t sh_map = sizeof(int) * (size_t)(s.lds_cap + 8);
     hipLaunchKernelGGL(k_half_fill, dim3(s.ntiles), dim3(kBlock), sh_map, st, s);
+    if (s.estore) hipLaunchKernelGGL(k_col_fill, dim3(s.ntiles), dim3(kBlock), sh_map, st, s);
     return hipGetLastError();
 }
 
@@ -2064,6 +2177,25 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
             hipLaunchKernelGGL(k_kick<0>, grid_n(s.n), dim3(kBlock), 0, st, s);
         }
         if (!kick) hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
+    } else if (mode == 3) {  // deterministic edge: per-edge results, then a gather
+        if (!s.estore) return hipErrorInvalidValue;
+        (void)launch_half_fill(s, st);  // launch errors surface in hipGetLastError below
+        dim3 g((unsigned)edge_grid), b(kBlock);
+        if (s.pot == 0) {
+            if (prec == 0) hipLaunchKernelGGL((k_edge<0, 0, true>), g, b, 0, st, s);
+            else hipLaunchKernelGGL((k_edge<0, 1, true>), g, b, 0, st, s);
+            hipLaunchKernelGGL(k_edge_gather<0>, grid_n(s.n), b, 0, st, s);
+        } else {
+            if (prec == 0) hipLaunchKernelGGL((k_edge<1, 0, true>), g, b, 0, st, s);
+            else hipLaunchKernelGGL((k_edge<1, 1, true>), g, b, 0, st, s);
+            hipLaunchKernelGGL(k_edge_gather<1>, grid_n(s.n), b, 0, st, s);
+        }
+        if (kick) {
+            if (s.pot == 0) hipLaunchKernelGGL(k_kick<0>, grid_n(s.n), dim3(kBlock), 0, st, s);
+            else hipLaunchKernelGGL(k_kick<1>, grid_n(s.n), dim3(kBlock), 0, st, s);
+        } else {
+            hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
+        }
     } else {
         (void)launch_half_fill(s, st);  // launch errors surface in hipGetLastError below
         if (!kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);

@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 MD_OK = 0
-MODE = {"vertex": 0, "edge": 1, "newton": 2}
+MODE = {"vertex": 0, "edge": 1, "newton": 2, "edge_det": 3}
 POT = {"lj": 0, "patchy": 1}
 PREC = {"fp64": 0, "fp32": 1, "fp32_kahan": 2}
 
@@ -38,7 +38,7 @@ class MDParams(ctypes.Structure):
                 ("eps_p", ctypes.c_double), ("patch_w", ctypes.c_double),
                 ("patch_delta", ctypes.c_double), ("patch_rcut", ctypes.c_double),
                 ("inertia", ctypes.c_double), ("newton_m", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("edge_store", ctypes.c_int32)]
 
 
 class MDSizes(ctypes.Structure):
@@ -126,11 +126,13 @@ def _dp(a):
     return None if a is None else a.ctypes.data_as(_D)
 
 
-def make_params(w, prec: str = "fp64", newton_m: int = 0) -> MDParams:
+def make_params(w, prec: str = "fp64", newton_m: int = 0, edge_store: bool = False) -> MDParams:
     """md_params from a Workload of paper_1401_4350_amd.inputs; newton_m is
-    the number of replicated force arrays of the Newton mode (0: LDS)."""
+    the number of replicated force arrays of the Newton mode (0: LDS);
+    edge_store reserves the per-edge arrays of the deterministic edge mode."""
     p = MDParams()
     p.newton_m = newton_m
+    p.edge_store = int(edge_store)
     p.n, p.pot, p.prec = w.n, POT[w.pot], PREC[prec]
     p.max_neighbors = w.list_capacity()
     p.box, p.eps, p.sigma, p.rcut, p.skin = w.box, w.eps, w.sigma, w.rcut, w.skin

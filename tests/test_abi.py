@@ -55,11 +55,22 @@ def test_query_sizes(md):
     assert s.workspace_bytes >= 4096 * 4 * _params(md).max_neighbors
 
 
+def test_edge_store_workspace(md):
+    """The deterministic edge mode's arrays are reserved only on request: 24 B
+    (LJ) per half-list entry plus 4 B per full-list slot."""
+    p0 = _params(md)
+    p1 = _params(md, edge_store=1)
+    s0, s1 = md.query_sizes(p0), md.query_sizes(p1)
+    assert s1.state_bytes == s0.state_bytes
+    half = p0.n * p0.max_neighbors // 2
+    assert s1.workspace_bytes - s0.workspace_bytes >= 24 * half + 4 * p0.n * p0.max_neighbors
+
+
 @pytest.mark.parametrize("field,value,status", [
     ("n", 1, -1), ("box", 5.0, -5), ("dt", 0.0, -1), ("skin", -0.1, -1),
     ("rcut", 0.0, -1), ("max_neighbors", 0, -1), ("mass", -1.0, -1), ("pot", 7, -1),
     ("prec", 9, -1), ("box", float("nan"), -1), ("newton_m", -1, -1), ("newton_m", 65, -1),
-    ("reserved", 1, -1),
+    ("edge_store", 2, -1), ("edge_store", -1, -1),
 ])
 def test_invalid_params_rejected_on_host(md, field, value, status):
     p = _params(md, **{field: value})
