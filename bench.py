@@ -33,15 +33,16 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 LJ_ENTRY_FLOPS = 23
 
 
-def vertex_step_bytes(n: int, pairs: int) -> int:
+def vertex_step_bytes(n: int, pairs: int, staged: float = 1.0) -> int:
     """Algorithmic bytes of one vertex force launch with the fused closing
     half kick and the next step's half kick and drift (LJ, FP64): every
-    full-list entry read once (4 B, 2|E| entries), per particle the list
-    length (4 B), its own position (24 B), the force written (24 B), the
-    velocity read and written (48 B), the build position read (24 B) and the
-    drifted position written (24 B).  Neighbour positions are gathers that the
-    method assumes are cache hits."""
-    return 8 * pairs + 148 * n
+    full-list entry read once (2|E| entries: 2 B region indices in tiles
+    staged in LDS, a fraction `staged` of them, 4 B slots elsewhere), per
+    particle the list length (4 B), its own position (24 B), the force
+    written (24 B), the velocity read and written (48 B), the build position
+    read (24 B) and the drifted position written (24 B).  Neighbour positions
+    are gathers that the method assumes are cache hits."""
+    return int(2 * pairs * (2 * staged + 4 * (1 - staged))) + 148 * n
 
 
 def edge_pass_bytes(n: int, pairs: int) -> int:
@@ -51,6 +52,16 @@ def edge_pass_bytes(n: int, pairs: int) -> int:
     kick (24 B), velocity read and written (48 B).  Atomic read-modify-write
     traffic is not counted here."""
     return 6 * pairs + 124 * n
+
+
+def edge_det_bytes(n: int, pairs: int) -> int:
+    """Algorithmic bytes of one deterministic edge pass + kick (LJ): the store
+    pass reads every half-list entry (4 B) and writes its force record (32 B);
+    the gather reads every full-list entry's edge index (4 B, 2|E|) and that
+    edge's record (32 B); per particle the row start (4 B), its own position
+    (24 B), the list length (4 B), forces written (24 B) and read back by the
+    kick (24 B), velocity read and written (48 B)."""
+    return 36 * pairs + 72 * pairs + 128 * n
 
 
 def newton_pass_bytes(n: int, pairs: int, m: int) -> int:
@@ -67,7 +78,7 @@ def newton_pass_bytes(n: int, pairs: int, m: int) -> int:
 
 
 def time_mode(md, torch, w, state, mode, prec, steps, warmup, newton_m=0):
-    g = md.System(md.make_params(w, prec, newton_m=newton_m))
+    g = md.System(md.make_params(w, prec, newton_m=newton_m, edge_store=mode == "edge_det"))
     g.set_state(state.x, state.v, state.q, state.angmom)
     g.build()
     g.forces(mode)
@@ -271,6 +282,9 @@ def main():
         for mode in ("vertex", "edge"):
             variants[f"{mode}_fp32"] = time_mode(md, torch, w, state, mode, "fp32",
                                                  args.steps, args.warmup)
+    if not args.no_variants:
+        variants["edge_det"] = time_mode(md, torch, w, state, "edge_det", args.prec,
+                                         args.steps, args.warmup)
     newton = {}
     if not args.no_variants and w.pot == "lj":
         for m in (0, 1, 4, 16):
@@ -280,7 +294,8 @@ def main():
     head = runs["vertex"]
     pairs = head["pairs"]
     value = pairs / (head["ms_per_step"] * 1e-3)
-    nb = vertex_step_bytes(w.n, pairs)
+    staged = head["tiles_staged"] / max(1, head["tiles_total"])
+    nb = vertex_step_bytes(w.n, pairs, staged)
     t_kernel = head["force_ms_per_step"] * 1e-3
     achieved = nb / t_kernel / 1e9
 
@@ -295,10 +310,15 @@ def main():
                 "tiles_staged": r["tiles_staged"], "tiles_total": r["tiles_total"],
                 "energy_per_particle": r["energy_per_particle"]}
 
-    modes = {"vertex": summary(runs["vertex"], vertex_step_bytes(w.n, runs["vertex"]["pairs"])),
+    modes = {"vertex": summary(runs["vertex"], nb),
              "edge": summary(runs["edge"], edge_pass_bytes(w.n, runs["edge"]["pairs"]))}
     for k, r in variants.items():
-        nbv = (vertex_step_bytes if k.startswith("vertex") else edge_pass_bytes)(w.n, r["pairs"])
+        if k.startswith("vertex"):
+            nbv = vertex_step_bytes(w.n, r["pairs"], r["tiles_staged"] / max(1, r["tiles_total"]))
+        elif k == "edge_det":
+            nbv = edge_det_bytes(w.n, r["pairs"])
+        else:
+            nbv = edge_pass_bytes(w.n, r["pairs"])
         modes[k] = summary(r, nbv)
     for m, r in newton.items():
         modes[f"newton_m{m}"] = summary(r, newton_pass_bytes(w.n, r["pairs"], m))

@@ -103,7 +103,7 @@ typedef struct {
     double inertia;        /* isotropic moment of inertia > 0                        */
     /* MD_MODE_NEWTON only */
     int32_t newton_m;      /* replicated force arrays, 1 .. 64; 0: LDS accumulation  */
-    int32_t edge_store;    /* 1: workspace for MD_MODE_EDGE_DET (8 B x 3 (LJ) or 9     */
+    int32_t edge_store;    /* 1: workspace for MD_MODE_EDGE_DET (32 B (LJ) or 96 B    */
                            /* (patchy) per half-list entry, 4 B per full-list slot);  */
                            /* 0: none.  Half-list capacity below 2^31 entries          */
 } md_params;

@@ -156,8 +156,8 @@ Layout layout(const md_params& p) {
     L.tmax = take(cur, 4 * (uint64_t)L.ntiles);
     // deterministic edge mode: per-edge results (F, and tau_i, tau_j for
     // patchy) and an edge index per full-list entry
-    const uint64_t ncomp = p.pot == MD_POT_LJ ? 3 : 9;
-    L.ef = take(cur, p.edge_store ? 8 * ncomp * (uint64_t)L.max_half : 0);
+    const uint64_t nrec = p.pot == MD_POT_LJ ? 1 : 3;
+    L.ef = take(cur, p.edge_store ? 32 * nrec * (uint64_t)L.max_half : 0);
     L.eidx = take(cur, p.edge_store ? 4 * (uint64_t)L.ntiles * ((p.max_neighbors + 3) / 4) * md::kTile * 4 : 0);
     L.sync = take(cur, 4 * (uint64_t)md::kSyncUses * md::kSyncInts);
     L.tile_seg = take(cur, 16 * (uint64_t)L.ntiles * md::kSegMax);
@@ -340,7 +340,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.bsum = (int*)(W + L.bsum);
     y.tmax = (int*)(W + L.tmax);
     y.estore = p->edge_store;
-    y.ef = p->edge_store ? (double*)(W + L.ef) : nullptr;
+    y.ef = p->edge_store ? (double4*)(W + L.ef) : nullptr;
     y.eidx = p->edge_store ? (int*)(W + L.eidx) : nullptr;
     y.sync = (int*)(W + L.sync);
     y.ntiles = L.ntiles;

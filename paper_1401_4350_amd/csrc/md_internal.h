@@ -123,7 +123,7 @@ struct Sys {
     // full-list entry, its half-list edge (bit 31 set: the particle is the
     // edge's second member; -1: none), tiled like 32-bit nbr entries
     int estore;
-    double* ef;      // [ncomp * max_half]: F on the second member, then (patchy) tau_i, tau_j
+    double4* ef;     // per edge: F on the second member, then (patchy) tau_i, tau_j
     int* eidx;
     int* sync;       // [kSyncUses * kSyncInts] completion counters
     int ntiles;      // ceil(n / kTile)

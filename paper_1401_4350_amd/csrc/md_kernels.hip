@@ -1069,12 +1069,16 @@ __device__ __forceinline__ void b_col_fill(const Sys& s, int bid, int nb) {
         const int j = nseg >= 0 ? map[row16[list_off16(kq)]] : entry_slot(row[list_off(kq)]);
         if (j >= i) continue;
         int v = -1;
-        const int e1 = s.hstart[j + 1];
-        for (int e = s.hstart[j]; e < e1; e++)
-            if (entry_slot(s.hj[e]) == i) {
-                v = e | INT_MIN;
-                break;
-            }
+        const int e0 = s.hstart[j], e1 = s.hstart[j + 1];
+        // eight entries of row j per round, all loads issued first
+        for (int b = e0; b < e1 && v == -1; b += 8) {
+            int h[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) h[u] = s.hj[min(b + u, e1 - 1)];
+#pragma unroll
+            for (int u = 7; u >= 0; u--)
+                if (b + u < e1 && entry_slot(h[u]) == i) v = (b + u) | INT_MIN;
+        }
         erow[list_off(kq)] = v;
     }
     if (last_block(s.sync + kSyncCol * kSyncInts, bid, nb) && threadIdx.x == 0) s.ctrl->eidx_stale = 0;
@@ -1551,18 +1555,12 @@ __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
         }
         if (STORE) {
             if (valid) {
-                const size_t H = (size_t)s.max_half;
-                double* ef = s.ef + e;
-                ef[0] = fx;
-                ef[H] = fy;
-                ef[2 * H] = fz;
+                constexpr int C = POT == 1 ? 3 : 1;  // records per edge
+                double4* ef = s.ef + (size_t)e * C;
+                ef[0] = make_double4(fx, fy, fz, 0.0);
                 if (POT == 1) {
-                    ef[3 * H] = tix;
-                    ef[4 * H] = tiy;
-                    ef[5 * H] = tiz;
-                    ef[6 * H] = tjx;
-                    ef[7 * H] = tjy;
-                    ef[8 * H] = tjz;
+                    ef[1] = make_double4(tix, tiy, tiz, 0.0);
+                    ef[2] = make_double4(tjx, tjy, tjz, 0.0);
                 }
             }
             continue;
@@ -1616,34 +1614,61 @@ __global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
     b_edge<POT, PREC, STORE>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
-// Deterministic edge mode, second pass: one thread per particle sums the
-// stored results of its edges in the order of its full list (-F as the
-// edge's first member, +F as its second; tau_i or tau_j), so the forces do
-// not depend on scheduling.  Writes F (and tau) for the closing kick.
+// Deterministic edge mode, second pass: four lanes per particle sum the
+// stored results of its edges (-F as the edge's first member, +F as its
+// second; tau_i or tau_j), lane q the entries q, q + 4, ... of its list in
+// order, then the four partial sums in a fixed order, so the forces do not
+// depend on scheduling.  Writes F (and tau) for the closing kick.
 template <int POT>
 __device__ __forceinline__ void b_edge_gather(const Sys& s, int bid, int nb) {
-    const int i = bid * kBlock + threadIdx.x;
-    if (i >= s.n) return;
-    const size_t H = (size_t)s.max_half;
-    const int cnt = s.ncount[i];
-    const int* erow = eidx_row(s, i);
+    constexpr int TPP = kTileTpp, U = 4, C = POT == 1 ? 3 : 1;
+    const int i = bid * kTile + threadIdx.x / TPP;
+    const int q = threadIdx.x % TPP;
+    const bool act = i < s.n;
+    const int ii = act ? i : s.n - 1;
+    const int cnt = act ? s.ncount[ii] : 0;
+    const int* erow = eidx_row(s, ii);
     double fx = 0, fy = 0, fz = 0, tx = 0, ty = 0, tz = 0;
-    for (int k = 0; k < cnt; k++) {
-        const int v = erow[list_off(k)];
-        if (v == -1) continue;
-        const size_t e = (size_t)(v & INT_MAX);
-        const bool second = v < 0;
-        const double g = second ? 1.0 : -1.0;
-        fx += g * s.ef[e];
-        fy += g * s.ef[H + e];
-        fz += g * s.ef[2 * H + e];
-        if (POT == 1) {
-            const size_t t0 = second ? 6 * H : 3 * H;
-            tx += s.ef[t0 + e];
-            ty += s.ef[t0 + H + e];
-            tz += s.ef[t0 + 2 * H + e];
+    for (int k0 = q; k0 < cnt; k0 += U * TPP) {
+        int v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int kk = k0 + u * TPP;
+            v[u] = kk < cnt ? erow[list_off(kk)] : -1;
+        }
+        double4 fe[U], te[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const size_t e = (size_t)(v[u] == -1 ? 0 : (v[u] & INT_MAX));
+            fe[u] = s.ef[e * C];
+            if (POT == 1) te[u] = s.ef[e * C + (v[u] < 0 ? 2 : 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (v[u] == -1) continue;
+            const double g = v[u] < 0 ? 1.0 : -1.0;
+            fx += g * fe[u].x;
+            fy += g * fe[u].y;
+            fz += g * fe[u].z;
+            if (POT == 1) {
+                tx += te[u].x;
+                ty += te[u].y;
+                tz += te[u].z;
+            }
         }
     }
+#pragma unroll
+    for (int off = 1; off < TPP; off <<= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+        if (POT == 1) {
+            tx += __shfl_xor(tx, off);
+            ty += __shfl_xor(ty, off);
+            tz += __shfl_xor(tz, off);
+        }
+    }
+    if (!act || q != 0) return;
     s.frc[i] = make_double4(fx, fy, fz, 0.0);
     if (POT == 1) s.trq[i] = make_double4(tx, ty, tz, 0.0);
     if (!isfinite(fx + fy + fz + tx + ty + tz)) atomicOr(&s.ctrl->nonfinite, 1);
@@ -2184,11 +2209,11 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
         if (s.pot == 0) {
             if (prec == 0) hipLaunchKernelGGL((k_edge<0, 0, true>), g, b, 0, st, s);
             else hipLaunchKernelGGL((k_edge<0, 1, true>), g, b, 0, st, s);
-            hipLaunchKernelGGL(k_edge_gather<0>, grid_n(s.n), b, 0, st, s);
+            hipLaunchKernelGGL(k_edge_gather<0>, dim3((unsigned)s.ntiles), b, 0, st, s);
         } else {
             if (prec == 0) hipLaunchKernelGGL((k_edge<1, 0, true>), g, b, 0, st, s);
             else hipLaunchKernelGGL((k_edge<1, 1, true>), g, b, 0, st, s);
-            hipLaunchKernelGGL(k_edge_gather<1>, grid_n(s.n), b, 0, st, s);
+            hipLaunchKernelGGL(k_edge_gather<1>, dim3((unsigned)s.ntiles), b, 0, st, s);
         }
         if (kick) {
             if (s.pot == 0) hipLaunchKernelGGL(k_kick<0>, grid_n(s.n), dim3(kBlock), 0, st, s);

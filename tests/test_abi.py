@@ -56,14 +56,14 @@ def test_query_sizes(md):
 
 
 def test_edge_store_workspace(md):
-    """The deterministic edge mode's arrays are reserved only on request: 24 B
+    """The deterministic edge mode's arrays are reserved only on request: 32 B
     (LJ) per half-list entry plus 4 B per full-list slot."""
     p0 = _params(md)
     p1 = _params(md, edge_store=1)
     s0, s1 = md.query_sizes(p0), md.query_sizes(p1)
     assert s1.state_bytes == s0.state_bytes
     half = p0.n * p0.max_neighbors // 2
-    assert s1.workspace_bytes - s0.workspace_bytes >= 24 * half + 4 * p0.n * p0.max_neighbors
+    assert s1.workspace_bytes - s0.workspace_bytes >= 32 * half + 4 * p0.n * p0.max_neighbors
 
 
 @pytest.mark.parametrize("field,value,status", [
