@@ -106,7 +106,23 @@ typedef struct {
     int32_t edge_store;    /* 1: workspace for MD_MODE_EDGE_DET (32 B (LJ) or 96 B    */
                            /* (patchy) per half-list entry, 4 B per full-list slot);  */
                            /* 0: none.  Half-list capacity below 2^31 entries          */
+    int32_t cell_order;    /* slot order of the cells (md_cell_order); the default 0  */
+                           /* stages tile regions in LDS, the others gather from      */
+                           /* global memory (locality study of the paper's Methods)   */
+    int32_t reserved;      /* must be 0                                              */
 } md_params;
+
+/* Order of the cells, and so of the particle slots after every list build.
+ * MD_CELLS_ROW_MAJOR stages each tile's neighbour region in LDS (the
+ * default); the others use global gathers, the setting the paper's Hilbert
+ * sort is about (Methods section: sorting particles along a space-filling
+ * curve for memory locality). */
+typedef enum {
+    MD_CELLS_ROW_MAJOR = 0,         /* x fastest, then y, then z; LDS-staged tiles       */
+    MD_CELLS_ROW_MAJOR_GATHER = 1,  /* the same order, every tile gathers from HBM       */
+    MD_CELLS_MORTON = 2,            /* Z order: interleaved bits of (x, y, z)            */
+    MD_CELLS_HILBERT = 3            /* 3-D Hilbert curve (Skilling's transposition)      */
+} md_cell_order;
 
 typedef struct {
     uint64_t state_bytes;     /* persistent particle state                       */
@@ -127,6 +143,13 @@ typedef struct {
 /* Sizes of the two device buffers a system needs (pure host, no HIP call).
  * Returns MD_ERR_INVALID_ARG / MD_ERR_BOX_TOO_SMALL for bad parameters. */
 md_status md_query_sizes(const md_params* p, md_sizes* out);
+
+/* Pure host, no HIP call: rank[(z * nc + y) * nc + x] = position of cell
+ * (x, y, z) of an nc^3 grid in the given order (a permutation of 0 .. nc^3-1;
+ * curves over the enclosing power-of-two cube, ranked).  `rank` holds nc^3
+ * ints, caller-owned.  MD_ERR_INVALID_ARG for nc < 1, nc > 1024 or an
+ * unknown order. */
+md_status md_cell_order_ranks(int32_t nc, int32_t order, int32_t* rank);
 
 /* Create a system on the current HIP device.  d_state and d_workspace are
  * device buffers of at least the sizes md_query_sizes reports, aligned to

@@ -30,7 +30,7 @@ struct Layout {
     uint64_t pos, vel, frc, quat, angm, trq, id;
     // workspace offsets
     uint64_t pos_alt, xbuild, tpos, tposf, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
-        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, tmax, sync, ef, eidx, epart, wpart, kpart, red, ctrl, tile_seg,
+        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, tmax, sync, ef, eidx, cell_rank, epart, wpart, kpart, red, ctrl, tile_seg,
         tile_nseg, tile_chunk, tile_nchunk, tile_row0;
     int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
     long long max_half = 0;
@@ -63,6 +63,8 @@ md_status validate(const md_params* p) {
     }
     if (p->newton_m < 0 || p->newton_m > 64 || (p->edge_store != 0 && p->edge_store != 1))
         return MD_ERR_INVALID_ARG;
+    if (p->cell_order < MD_CELLS_ROW_MAJOR || p->cell_order > MD_CELLS_HILBERT || p->reserved != 0)
+        return MD_ERR_INVALID_ARG;
     // edge indices of the deterministic edge mode are 31-bit
     if (p->edge_store && (long long)p->n * p->max_neighbors / 2 + 4096 >= (long long)INT_MAX)
         return MD_ERR_INVALID_ARG;
@@ -77,6 +79,66 @@ md_status validate(const md_params* p) {
 }  // namespace
 
 namespace {
+
+// Curve index of cell (x, y, z) in a 2^b cube.  Morton: the bits of x, y, z
+// interleaved (x lowest).  Hilbert: Skilling's transposition (Programming the
+// Hilbert curve, AIP Conf. Proc. 707, 2004): undo the excess work of the
+// recursive reflections and exchanges from the top bit down, Gray-encode
+// across the axes, then interleave the transposed bits (first axis highest).
+uint64_t morton3(uint32_t x, uint32_t y, uint32_t z, int b) {
+    uint64_t h = 0;
+    for (int k = 0; k < b; k++)
+        h |= (uint64_t)((x >> k) & 1) << (3 * k) | (uint64_t)((y >> k) & 1) << (3 * k + 1) |
+             (uint64_t)((z >> k) & 1) << (3 * k + 2);
+    return h;
+}
+
+uint64_t hilbert3(uint32_t x, uint32_t y, uint32_t z, int b) {
+    uint32_t X[3] = {x, y, z};
+    if (b > 0) {
+        const uint32_t m = 1u << (b - 1);
+        for (uint32_t q = m; q > 1; q >>= 1) {
+            const uint32_t p = q - 1;
+            for (int i = 0; i < 3; i++) {
+                if (X[i] & q) {
+                    X[0] ^= p;  // invert the low bits of the first axis
+                } else {        // exchange the low bits of the first axis and axis i
+                    const uint32_t t = (X[0] ^ X[i]) & p;
+                    X[0] ^= t;
+                    X[i] ^= t;
+                }
+            }
+        }
+        for (int i = 1; i < 3; i++) X[i] ^= X[i - 1];  // Gray encode
+        uint32_t t = 0;
+        for (uint32_t q = m; q > 1; q >>= 1)
+            if (X[2] & q) t ^= q - 1;
+        for (int i = 0; i < 3; i++) X[i] ^= t;
+    }
+    uint64_t h = 0;
+    for (int k = b - 1; k >= 0; k--)
+        for (int i = 0; i < 3; i++) h = h << 1 | ((X[i] >> k) & 1);
+    return h;
+}
+
+void cell_ranks(int nc, int order, int* rank) {
+    const int nn = nc * nc * nc;
+    if (order == MD_CELLS_ROW_MAJOR || order == MD_CELLS_ROW_MAJOR_GATHER) {
+        for (int c = 0; c < nn; c++) rank[c] = c;
+        return;
+    }
+    int b = 0;
+    while ((1 << b) < nc) b++;
+    std::vector<std::pair<uint64_t, int>> key(nn);
+    for (int z = 0; z < nc; z++)
+        for (int y = 0; y < nc; y++)
+            for (int x = 0; x < nc; x++) {
+                const int c = (z * nc + y) * nc + x;
+                key[c] = {order == MD_CELLS_MORTON ? morton3(x, y, z, b) : hilbert3(x, y, z, b), c};
+            }
+    std::sort(key.begin(), key.end());
+    for (int r = 0; r < nn; r++) rank[key[r].second] = r;
+}
 
 // Band of the FP32 list test around r_v^2.  A record is rounded to FP32 from
 // [0, L), x_i minus an image shift from [-L, 2L), and their difference once
@@ -154,6 +216,7 @@ Layout layout(const md_params& p) {
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
     L.bsum = take(cur, 4 * (uint64_t)std::max(L.nblk, L.ntiles));  // per-tile half totals
     L.tmax = take(cur, 4 * (uint64_t)L.ntiles);
+    L.cell_rank = take(cur, p.cell_order >= MD_CELLS_MORTON ? 4 * (uint64_t)L.ncell : 0);
     // deterministic edge mode: per-edge results (F, and tau_i, tau_j for
     // patchy) and an edge index per full-list entry
     const uint64_t nrec = p.pot == MD_POT_LJ ? 1 : 3;
@@ -253,6 +316,13 @@ struct md_system {
 
 extern "C" {
 
+md_status md_cell_order_ranks(int32_t nc, int32_t order, int32_t* rank) {
+    if (!rank || nc < 1 || nc > 1024 || order < MD_CELLS_ROW_MAJOR || order > MD_CELLS_HILBERT)
+        return MD_ERR_INVALID_ARG;
+    cell_ranks(nc, order, rank);
+    return MD_OK;
+}
+
 md_status md_query_sizes(const md_params* p, md_sizes* out) {
     if (!out) return MD_ERR_INVALID_ARG;
     md_status st = validate(p);
@@ -340,6 +410,8 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.bsum = (int*)(W + L.bsum);
     y.tmax = (int*)(W + L.tmax);
     y.estore = p->edge_store;
+    y.cell_order = p->cell_order;
+    y.cell_rank = p->cell_order >= MD_CELLS_MORTON ? (const int*)(W + L.cell_rank) : nullptr;
     y.ef = p->edge_store ? (double4*)(W + L.ef) : nullptr;
     y.eidx = p->edge_store ? (int*)(W + L.eidx) : nullptr;
     y.sync = (int*)(W + L.sync);
@@ -366,6 +438,14 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     if (st == MD_OK) st = s->hip(hipMemsetAsync(d_state, 0, L.state_bytes, s->stream), "clear state");
     if (st == MD_OK && y.nrep > 0)  // replicas start at zero; the combining pass re-zeroes them
         st = s->hip(hipMemsetAsync(y.rep, 0, 32 * (size_t)p->n * y.nrep, s->stream), "clear replicas");
+    std::vector<int> ranks;  // cell order table, copied before the stream is drained
+    if (st == MD_OK && y.cell_rank) {
+        ranks.resize(L.ncell);
+        cell_ranks(L.nc, p->cell_order, ranks.data());
+        st = s->hip(hipMemcpyAsync((void*)y.cell_rank, ranks.data(), 4 * (size_t)L.ncell,
+                                   hipMemcpyHostToDevice, s->stream),
+                    "cell order");
+    }
     if (st == MD_OK) st = s->hip(md::launch_clear_ctrl(y, s->stream), "clear control");
     if (st == MD_OK) st = s->hip(hipStreamSynchronize(s->stream), "create sync");
     if (st != MD_OK) {

@@ -138,6 +138,8 @@ struct Sys {
     double* kpart;   // per-particle kinetic energy
     double* red;     // reduction partials (3 * kRedBlocks) + result (3)
     Ctrl* ctrl;
+    int cell_order;  // md_cell_order; nonzero: no tile staged in LDS
+    const int* cell_rank;  // curve orders: cell id of row-major cell (z * nc + y) * nc + x
     int eblk;        // blocks of the edge pass (grid-stride over the half list)
     int prec;        // md_precision of the pair maths
 };

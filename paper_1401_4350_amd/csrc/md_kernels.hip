@@ -381,6 +381,7 @@ __device__ __forceinline__ void b_cell_bin(const Sys& s, int bid, int nb) {
         const int cy = cell_coord(wrap_box(x.y, s.box), s.cell_inv, s.nc);
         const int cz = cell_coord(wrap_box(x.z, s.box), s.cell_inv, s.nc);
         c = (cz * s.nc + cy) * s.nc + cx;
+        if (s.cell_rank) c = s.cell_rank[c];  // cells along a space-filling curve
         s.cell[p] = c;
     }
     // group the lanes by cell (no memory traffic), then one atomic per group,
@@ -479,7 +480,7 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane) {
 __device__ __forceinline__ void b_tile_region(const Sys& s, int t) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nc = s.nc;
-    if (nc < 3 || s.pot != 0) {  // the patchy pass gathers from global memory
+    if (nc < 3 || s.pot != 0 || s.cell_order != 0) {  // gathers from global memory
         if (lane == 0) s.tile_nseg[t] = -1;
         return;
     }
@@ -871,8 +872,9 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
         if (act && (unsigned)hr > 1u) atomicOr(&s.ctrl->overflow, 2);  // region misses the particle
     } else {
         // Global gathers: every lane walks its own 27 cells as runs of
-        // consecutive slots (one or two per row of cells) and stores slot
-        // entries with the minimum-image code.
+        // consecutive slots (one or two per row of cells; cell by cell when
+        // the cells follow a space-filling curve) and stores slot entries
+        // with the minimum-image code.
         const int span = nc >= 3 ? 3 : nc;  // distinct cells per dimension
         const int lo = nc >= 3 ? -1 : 0;
         for (int dz = 0; dz < span; dz++) {
@@ -895,9 +897,19 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
                     if (nc == 2) a1 = b1 = 1 - cx;
                 }
                 const int rowbase = (az * nc + ay) * nc;
+                if (s.cell_rank) nr = span;  // one run per cell
                 for (int run = 0; run < nr; run++) {
-                    const int cb = act ? s.cstart[rowbase + (run ? a1 : a0)] : 0;
-                    const int ce = act ? s.cstart[rowbase + (run ? b1 : b0) + 1] : 0;
+                    int cb, ce;
+                    if (s.cell_rank) {
+                        int ax = cx + lo + run;
+                        ax = ax < 0 ? ax + nc : (ax >= nc ? ax - nc : ax);
+                        const int cid = s.cell_rank[rowbase + ax];
+                        cb = act ? s.cstart[cid] : 0;
+                        ce = act ? s.cstart[cid + 1] : 0;
+                    } else {
+                        cb = act ? s.cstart[rowbase + (run ? a1 : a0)] : 0;
+                        ce = act ? s.cstart[rowbase + (run ? b1 : b0) + 1] : 0;
+                    }
                     auto consider = [&](int j, const double4& pj) {
                         const double ex = pj.x - xi.x, ey = pj.y - xi.y, ez = pj.z - xi.z;
                         const double ddx = wrap_delta(ex, s.box, s.inv_box);

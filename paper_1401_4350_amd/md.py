@@ -38,7 +38,8 @@ class MDParams(ctypes.Structure):
                 ("eps_p", ctypes.c_double), ("patch_w", ctypes.c_double),
                 ("patch_delta", ctypes.c_double), ("patch_rcut", ctypes.c_double),
                 ("inertia", ctypes.c_double), ("newton_m", ctypes.c_int32),
-                ("edge_store", ctypes.c_int32)]
+                ("edge_store", ctypes.c_int32), ("cell_order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class MDSizes(ctypes.Structure):
@@ -79,6 +80,7 @@ _I64P = ctypes.POINTER(ctypes.c_int64)
 
 _SIGS = {
     "md_query_sizes": ([ctypes.POINTER(MDParams), ctypes.POINTER(MDSizes)], ctypes.c_int),
+    "md_cell_order_ranks": ([ctypes.c_int32, ctypes.c_int32, _I32P], ctypes.c_int),
     "md_create": ([ctypes.POINTER(MDParams), _P, ctypes.c_uint64, _P, ctypes.c_uint64, _P,
                    ctypes.POINTER(_sys_p)], ctypes.c_int),
     "md_set_state": ([_sys_p, _D, _D, _D, _D], ctypes.c_int),
@@ -126,13 +128,19 @@ def _dp(a):
     return None if a is None else a.ctypes.data_as(_D)
 
 
-def make_params(w, prec: str = "fp64", newton_m: int = 0, edge_store: bool = False) -> MDParams:
+CELL_ORDER = {"row_major": 0, "row_major_gather": 1, "morton": 2, "hilbert": 3}
+
+
+def make_params(w, prec: str = "fp64", newton_m: int = 0, edge_store: bool = False,
+                cell_order: str = "row_major") -> MDParams:
     """md_params from a Workload of paper_1401_4350_amd.inputs; newton_m is
     the number of replicated force arrays of the Newton mode (0: LDS);
-    edge_store reserves the per-edge arrays of the deterministic edge mode."""
+    edge_store reserves the per-edge arrays of the deterministic edge mode;
+    cell_order is the slot order of the cells (CELL_ORDER)."""
     p = MDParams()
     p.newton_m = newton_m
     p.edge_store = int(edge_store)
+    p.cell_order = CELL_ORDER[cell_order]
     p.n, p.pot, p.prec = w.n, POT[w.pot], PREC[prec]
     p.max_neighbors = w.list_capacity()
     p.box, p.eps, p.sigma, p.rcut, p.skin = w.box, w.eps, w.sigma, w.rcut, w.skin
@@ -140,6 +148,16 @@ def make_params(w, prec: str = "fp64", newton_m: int = 0, edge_store: bool = Fal
     p.eps_p, p.patch_w, p.patch_delta = w.eps_p, w.patch_w, w.patch_delta
     p.patch_rcut, p.inertia = w.patch_rcut, w.inertia
     return p
+
+
+def cell_order_ranks(nc: int, order: str) -> np.ndarray:
+    """Position of every cell of an nc^3 grid (row-major index) in the given
+    cell order (md_cell_order_ranks)."""
+    out = np.zeros(nc ** 3, dtype=np.int32)
+    st = _lib.md_cell_order_ranks(nc, CELL_ORDER[order], out.ctypes.data_as(_I32P))
+    if st != MD_OK:
+        raise MDError(st, "md_cell_order_ranks")
+    return out
 
 
 def query_sizes(p: MDParams) -> MDSizes:

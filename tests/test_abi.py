@@ -70,7 +70,8 @@ def test_edge_store_workspace(md):
     ("n", 1, -1), ("box", 5.0, -5), ("dt", 0.0, -1), ("skin", -0.1, -1),
     ("rcut", 0.0, -1), ("max_neighbors", 0, -1), ("mass", -1.0, -1), ("pot", 7, -1),
     ("prec", 9, -1), ("box", float("nan"), -1), ("newton_m", -1, -1), ("newton_m", 65, -1),
-    ("edge_store", 2, -1), ("edge_store", -1, -1),
+    ("edge_store", 2, -1), ("edge_store", -1, -1), ("cell_order", 4, -1), ("cell_order", -1, -1),
+    ("reserved", 1, -1),
 ])
 def test_invalid_params_rejected_on_host(md, field, value, status):
     p = _params(md, **{field: value})
