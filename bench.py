@@ -77,8 +77,9 @@ def newton_pass_bytes(n: int, pairs: int, m: int) -> int:
     return 4 * pairs + n * (4 + 24 + 48 + 24 + 24 + 64 * m + 24)
 
 
-def time_mode(md, torch, w, state, mode, prec, steps, warmup, newton_m=0):
-    g = md.System(md.make_params(w, prec, newton_m=newton_m, edge_store=mode == "edge_det"))
+def time_mode(md, torch, w, state, mode, prec, steps, warmup, newton_m=0, cell_order="row_major"):
+    g = md.System(md.make_params(w, prec, newton_m=newton_m, edge_store=mode == "edge_det",
+                                 cell_order=cell_order))
     g.set_state(state.x, state.v, state.q, state.angmom)
     g.build()
     g.forces(mode)
@@ -186,6 +187,29 @@ def crossover_bench(torch, steps=100, warmup=20):
     return points
 
 
+def locality_bench(torch, steps=100, warmup=20):
+    """Slot order of the cells against the force pass (FP64): row-major cells
+    with LDS-staged tiles (the default), and row-major, Morton and Hilbert
+    cell orders with every neighbour gathered from global memory, for the LJ
+    and the patchy workload, vertex and edge."""
+    from paper_1401_4350_amd import md
+    from paper_1401_4350_amd.inputs import WORKLOADS, make_state
+    rows = []
+    for base in ("lj_many", "patchy"):
+        w = WORKLOADS[base]
+        st = make_state(w, 1)
+        for order in ("row_major", "row_major_gather", "morton", "hilbert"):
+            row = {"workload": base, "cell_order": order}
+            for mode in ("vertex", "edge"):
+                r = time_mode(md, torch, w, st, mode, "fp64", steps, warmup, cell_order=order)
+                row[f"{mode}_step_us"] = 1e3 * r["ms_per_step"]
+                row[f"{mode}_force_us"] = 1e3 * r["force_ms_per_step"]
+                row["tiles_staged"] = r["tiles_staged"]
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    return rows
+
+
 def drift_bench(torch, steps=10000, every=500):
     """Total-energy drift of the 1M-particle LJ workload (dt = 0.005) over
     `steps` velocity-Verlet steps for each precision variant: slope of a
@@ -241,6 +265,8 @@ def main():
     ap.add_argument("--serving-steps", type=int, default=1000)
     ap.add_argument("--crossover", action="store_true",
                     help="print the vertex/edge crossover sweep instead of the headline line")
+    ap.add_argument("--locality", action="store_true",
+                    help="cell orders (row-major staged / gathered, Morton, Hilbert) instead of the bench line")
     ap.add_argument("--drift", action="store_true",
                     help="print the energy-drift study of the precision variants instead")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -263,6 +289,9 @@ def main():
         return
     if args.drift:
         print(json.dumps({"drift": drift_bench(torch)}), flush=True)
+        return
+    if args.locality:
+        print(json.dumps({"locality": locality_bench(torch)}), flush=True)
         return
     w = WORKLOADS[args.workload]
     state = make_state(w, args.seed)
