@@ -33,16 +33,17 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 LJ_ENTRY_FLOPS = 23
 
 
-def vertex_step_bytes(n: int, pairs: int, staged: float = 1.0) -> int:
+def vertex_step_bytes(n: int, pairs: int) -> int:
     """Algorithmic bytes of one vertex force launch with the fused closing
     half kick and the next step's half kick and drift (LJ, FP64): every
-    full-list entry read once (2|E| entries: 2 B region indices in tiles
-    staged in LDS, a fraction `staged` of them, 4 B slots elsewhere), per
-    particle the list length (4 B), its own position (24 B), the force
-    written (24 B), the velocity read and written (48 B), the build position
-    read (24 B) and the drifted position written (24 B).  Neighbour positions
-    are gathers that the method assumes are cache hits."""
-    return int(2 * pairs * (2 * staged + 4 * (1 - staged))) + 148 * n
+    full-list entry read once as a 4-byte index (2|E| entries; the kernel
+    itself reads 2-byte region indices in tiles staged in LDS, so its list
+    traffic is half of this), per particle the list length (4 B), its own
+    position (24 B), the force written (24 B), the velocity read and written
+    (48 B), the build position read (24 B) and the drifted position written
+    (24 B).  Neighbour positions are gathers that the method assumes are
+    cache hits."""
+    return 8 * pairs + 148 * n
 
 
 def edge_pass_bytes(n: int, pairs: int) -> int:
@@ -323,8 +324,7 @@ def main():
     head = runs["vertex"]
     pairs = head["pairs"]
     value = pairs / (head["ms_per_step"] * 1e-3)
-    staged = head["tiles_staged"] / max(1, head["tiles_total"])
-    nb = vertex_step_bytes(w.n, pairs, staged)
+    nb = vertex_step_bytes(w.n, pairs)
     t_kernel = head["force_ms_per_step"] * 1e-3
     achieved = nb / t_kernel / 1e9
 
@@ -343,7 +343,7 @@ def main():
              "edge": summary(runs["edge"], edge_pass_bytes(w.n, runs["edge"]["pairs"]))}
     for k, r in variants.items():
         if k.startswith("vertex"):
-            nbv = vertex_step_bytes(w.n, r["pairs"], r["tiles_staged"] / max(1, r["tiles_total"]))
+            nbv = vertex_step_bytes(w.n, r["pairs"])
         elif k == "edge_det":
             nbv = edge_det_bytes(w.n, r["pairs"])
         else:
