@@ -39,7 +39,7 @@ class PatchyParams(ctypes.Structure):
     _fields_ = [("eps", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("rcut", ctypes.c_double), ("eps_p", ctypes.c_double),
                 ("w", ctypes.c_double), ("delta", ctypes.c_double),
-                ("rpc", ctypes.c_double)]
+                ("rpc", ctypes.c_double), ("model", ctypes.c_int)]
 
 
 class RunParams(ctypes.Structure):
@@ -113,7 +113,9 @@ class LJ:
 
 @dataclass
 class Patchy:
-    """Four-patch model parameters (reading stated in oracle.c)."""
+    """Patchy model parameters (readings stated in oracle.c): model 0 is the
+    four-patch variant (defaults), model 1 the paper's two-patch model (use
+    Patchy.paper())."""
     eps: float = 1.0
     sigma: float = 1.0
     rcut: float = 1.5
@@ -121,10 +123,17 @@ class Patchy:
     w: float = 0.12
     delta: float = 0.5
     rpc: float = 0.75
+    model: int = 0
+
+    @staticmethod
+    def paper() -> "Patchy":
+        """Two polar patches, (sigma/r)^200 core, patch range 0.18 sigma."""
+        return Patchy(eps=1.0, sigma=1.0, rcut=1.18, eps_p=1.0, w=0.12, delta=0.5, rpc=0.18,
+                      model=1)
 
     def c(self) -> PatchyParams:
         return PatchyParams(self.eps, self.sigma, self.rcut, self.eps_p, self.w,
-                            self.delta, self.rpc)
+                            self.delta, self.rpc, self.model)
 
 
 def min_image(d: float, L: float) -> float:

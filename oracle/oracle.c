@@ -401,9 +401,99 @@ static double patchy_pair_impl(const double* xi, const double* xj, const double*
     return V;
 }
 
+/*
+ * Two-patch model of the paper's Eqs. 2-4 (M = 2), in the reading used here:
+ * the sign of the patch term's exponent is restored so that the attraction
+ * decays, its power n is 10, and the two patches sit at the poles of the body
+ * z axis, a distance delta from the centre:
+ *
+ *   V_ij = (sigma / r)^200 - eps_p sum_a sum_b exp(-1/2 (s_ab / w)^10) [s_ab < rpc]
+ *   for r < rcut, with d_ab = r_ij + delta (u_j^b - u_i^a), s_ab = |d_ab|,
+ *   u^0 = R(q) z_hat, u^1 = -R(q) z_hat.
+ *
+ * With w = 0.12 sigma and rpc = 0.18 sigma the truncated patch term is
+ * eps_p exp(-1/2 1.5^10) = 3.0e-13 eps_p; rcut = 2 delta + rpc covers every
+ * patch pair.  dV/dd_ab of a patch pair is 5 eps_p E (s/w)^8 / w^2 d_ab with
+ * E = exp(-1/2 (s/w)^10); the core gives dV/dr = -200 (sigma/r)^200 r_ij / r^2.
+ */
+static double patchy2_pair_impl(const double* xi, const double* xj, const double* qi,
+                                const double* qj, double L, const or_patchy_params* p,
+                                double* Fj, double* ti, double* tj, double* fmag, double* timag) {
+    double d[3];
+    for (int c = 0; c < 3; c++) {
+        d[c] = or_min_image(xj[c] - xi[c], L);
+        Fj[c] = ti[c] = tj[c] = 0;
+    }
+    double r2 = dot(d, d);
+    if (!(r2 < p->rcut * p->rcut)) return 0.0;
+    double V = 0, dVdr[3] = {0, 0, 0};
+
+    /* core */
+    double vc = pow(p->sigma * p->sigma / r2, 100.0);
+    V += vc;
+    for (int c = 0; c < 3; c++) {
+        double t = -200.0 * vc / r2 * d[c];
+        dVdr[c] += t;
+        if (fmag) fmag[c] += fabs(t);
+    }
+
+    double Ri[9], Rj[9], ui[2][3], uj[2][3];
+    or_quat_to_matrix(qi, Ri);
+    or_quat_to_matrix(qj, Rj);
+    for (int c = 0; c < 3; c++) {
+        ui[0][c] = Ri[3 * c + 2];
+        ui[1][c] = -Ri[3 * c + 2];
+        uj[0][c] = Rj[3 * c + 2];
+        uj[1][c] = -Rj[3 * c + 2];
+    }
+    double dVdui[2][3], dVduj[2][3];
+    memset(dVdui, 0, sizeof dVdui);
+    memset(dVduj, 0, sizeof dVduj);
+    double w2 = p->w * p->w;
+    for (int a = 0; a < 2; a++) {
+        for (int b = 0; b < 2; b++) {
+            double dab[3];
+            for (int c = 0; c < 3; c++) dab[c] = d[c] + p->delta * (uj[b][c] - ui[a][c]);
+            double s2 = dot(dab, dab);
+            if (p->rpc > 0 && !(s2 < p->rpc * p->rpc)) continue;
+            double x = s2 / w2;               /* (s/w)^2 */
+            double x4 = x * x * x * x;        /* (s/w)^8 */
+            double E = exp(-0.5 * x4 * x);    /* exp(-1/2 (s/w)^10) */
+            V += -p->eps_p * E;
+            double k = 5.0 * p->eps_p * E * x4 / w2;  /* dV/dd_ab = k d_ab */
+            for (int c = 0; c < 3; c++) {
+                dVdr[c] += k * dab[c];
+                dVdui[a][c] += -p->delta * k * dab[c];
+                dVduj[b][c] += p->delta * k * dab[c];
+            }
+            if (fmag && timag) {
+                double m[3], t[3];
+                for (int c = 0; c < 3; c++) {
+                    fmag[c] += fabs(k * dab[c]);
+                    m[c] = p->delta * k * dab[c];
+                }
+                cross(ui[a], m, t);
+                for (int c = 0; c < 3; c++) timag[c] += fabs(t[c]);
+            }
+        }
+    }
+    for (int c = 0; c < 3; c++) Fj[c] = -dVdr[c];
+    for (int a = 0; a < 2; a++) {
+        double m[3], t[3];
+        for (int c = 0; c < 3; c++) m[c] = -dVdui[a][c];
+        cross(ui[a], m, t);
+        for (int c = 0; c < 3; c++) ti[c] += t[c];
+        for (int c = 0; c < 3; c++) m[c] = -dVduj[a][c];
+        cross(uj[a], m, t);
+        for (int c = 0; c < 3; c++) tj[c] += t[c];
+    }
+    return V;
+}
+
 double or_patchy_pair(const double* xi, const double* xj, const double* qi,
                       const double* qj, double L, const or_patchy_params* p, double* Fj,
                       double* ti, double* tj) {
+    if (p->model == 1) return patchy2_pair_impl(xi, xj, qi, qj, L, p, Fj, ti, tj, NULL, NULL);
     return patchy_pair_impl(xi, xj, qi, qj, L, p, Fj, ti, tj, NULL, NULL);
 }
 
@@ -411,8 +501,11 @@ static void patchy_accumulate(const double* x, const double* q, int i, int j, do
                               const or_patchy_params* p, double* f3, double* t3,
                               double* e, double* w, double* fa, double* ta) {
     double Fj[3], ti[3], tj[3], d[3];
-    double v = patchy_pair_impl(&x[3 * i], &x[3 * j], &q[4 * i], &q[4 * j], L, p, Fj, ti, tj,
-                                fa, ta);
+    double v = p->model == 1
+                   ? patchy2_pair_impl(&x[3 * i], &x[3 * j], &q[4 * i], &q[4 * j], L, p, Fj, ti, tj,
+                                       fa, ta)
+                   : patchy_pair_impl(&x[3 * i], &x[3 * j], &q[4 * i], &q[4 * j], L, p, Fj, ti, tj,
+                                      fa, ta);
     for (int c = 0; c < 3; c++) {
         f3[c] -= Fj[c];
         t3[c] += ti[c];

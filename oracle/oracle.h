@@ -89,6 +89,9 @@ typedef struct {
     double w;          /* Gaussian patch width                  */
     double delta;      /* patch distance from the centre        */
     double rpc;        /* patch-patch cut-off (<=0: none)       */
+    int model;         /* 0: four patches, WCA core, cosine     */
+                       /*    factors; 1: two polar patches,     */
+                       /*    (sigma/r)^200 core (see oracle.c)  */
 } or_patchy_params;
 
 /* Rotation matrix of a unit Hamilton quaternion q=(w,x,y,z), row-major. */
