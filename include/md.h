@@ -74,6 +74,21 @@ typedef enum {
 } md_status;
 
 typedef enum { MD_POT_LJ = 0, MD_POT_PATCHY = 1 } md_potential;
+
+/* Patch geometry and pair potential of MD_POT_PATCHY (md_params.patch_model).
+ * d = x_j - x_i, u the unit patch directions, d_ab = d + patch_delta (u_j^b - u_i^a),
+ * s_ab = |d_ab|; every term vanishes beyond rcut, patch terms also for
+ * s_ab >= patch_rcut when patch_rcut > 0. */
+typedef enum {
+    /* four tetrahedral patches; WCA core of (eps, sigma) plus, for facing
+     * patches (u_i^a . d > 0 and u_j^b . d < 0),
+     * -eps_p exp(-s_ab^2 / w^2) cos^2(theta_i^a) cos^2(theta_j^b) */
+    MD_PATCH_TETRA = 0,
+    /* the paper's model (Eqs. 2-4 with M = 2): two patches at the poles
+     * +-R(q) e_z; core (sigma/r)^200 plus -eps_p exp(-(s_ab / w)^10 / 2) per
+     * patch pair (w = patch_w) */
+    MD_PATCH_POLAR2 = 1
+} md_patch_model;
 typedef enum { MD_MODE_VERTEX = 0, MD_MODE_EDGE = 1, MD_MODE_NEWTON = 2, MD_MODE_EDGE_DET = 3 } md_mode;
 
 /* Arithmetic of the pair forces.  Positions, velocities and the integrator are
@@ -97,7 +112,7 @@ typedef struct {
     double dt;             /* time step > 0                                          */
     /* patchy particles (MD_POT_PATCHY) only */
     double eps_p;          /* patch-patch strength                                   */
-    double patch_w;        /* Gaussian width of the patch attraction                 */
+    double patch_w;        /* width w of the patch attraction                        */
     double patch_delta;    /* distance of a patch from the particle centre           */
     double patch_rcut;     /* patch-patch cut-off; <= 0 means none                    */
     double inertia;        /* isotropic moment of inertia > 0                        */
@@ -109,7 +124,7 @@ typedef struct {
     int32_t cell_order;    /* slot order of the cells (md_cell_order); the default 0  */
                            /* stages tile regions in LDS, the others gather from      */
                            /* global memory (locality study of the paper's Methods)   */
-    int32_t reserved;      /* must be 0                                              */
+    int32_t patch_model;   /* md_patch_model (MD_POT_PATCHY); 0 for MD_POT_LJ         */
 } md_params;
 
 /* Order of the cells, and so of the particle slots after every list build.

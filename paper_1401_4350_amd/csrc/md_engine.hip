@@ -63,7 +63,10 @@ md_status validate(const md_params* p) {
     }
     if (p->newton_m < 0 || p->newton_m > 64 || (p->edge_store != 0 && p->edge_store != 1))
         return MD_ERR_INVALID_ARG;
-    if (p->cell_order < MD_CELLS_ROW_MAJOR || p->cell_order > MD_CELLS_HILBERT || p->reserved != 0)
+    if (p->cell_order < MD_CELLS_ROW_MAJOR || p->cell_order > MD_CELLS_HILBERT)
+        return MD_ERR_INVALID_ARG;
+    if (p->patch_model != MD_PATCH_TETRA &&
+        (p->pot != MD_POT_PATCHY || p->patch_model != MD_PATCH_POLAR2))
         return MD_ERR_INVALID_ARG;
     // edge indices of the deterministic edge mode are 31-bit
     if (p->edge_store && (long long)p->n * p->max_neighbors / 2 + 4096 >= (long long)INT_MAX)
@@ -376,7 +379,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.inv_mass = 1.0 / p->mass;
     y.inv_inertia = patchy ? 1.0 / p->inertia : 0.0;
     md::set_potential(y, p->eps, p->sigma, p->rcut, p->eps_p, patchy ? p->patch_w : 1.0,
-                      p->patch_delta, p->patch_rcut);
+                      p->patch_delta, p->patch_rcut, p->patch_model);
     y.pos = (double4*)(S + L.pos);
     y.vel = (double4*)(S + L.vel);
     y.frc = (double4*)(S + L.frc);

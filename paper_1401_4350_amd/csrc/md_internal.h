@@ -61,6 +61,7 @@ template <typename R>
 struct PatchyC {
     R sig2, eps4, eps24, eps, wca2;  // WCA core
     R eps_p, inv_w2, delta, rpc2;    // patches (rpc2 <= 0: no patch cut-off)
+    int model;                       // 0: four patches, WCA, cosine factors; 1: two polar patches
 };
 
 // Everything a kernel needs, passed by value.  Particle arrays are packed
@@ -235,6 +236,6 @@ hipError_t launch_clear_rebuild(const Sys& s, hipStream_t st);
 
 // Fills the potential constants of s from the physical parameters.
 void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, double w,
-                   double delta, double rpc);
+                   double delta, double rpc, int patch_model);
 
 }  // namespace md

@@ -143,15 +143,23 @@ __device__ __forceinline__ R dot3(const V3<R>& a, const V3<R>& b) {
     return a.x * b.x + a.y * b.y + a.z * b.z;
 }
 
-// The four tetrahedral patch directions of a particle with orientation
-// q = (w, x, y, z): u_a = R(q) e_a with e_a = (+-1, +-1, +-1)/sqrt(3) having an
-// even number of minus signs, i.e. sums and differences of R's columns.
+// The patch directions of a particle with orientation q = (w, x, y, z).
+// Model 0: the four tetrahedral directions u_a = R(q) e_a with
+// e_a = (+-1, +-1, +-1)/sqrt(3) having an even number of minus signs, i.e. sums
+// and differences of R's columns.  Model 1: the two poles +-R(q) e_z (u[2],
+// u[3] unused).
 template <typename R>
-__device__ __forceinline__ void patch_dirs(const double4& q, V3<R> u[4]) {
+__device__ __forceinline__ void patch_dirs(const double4& q, V3<R> u[4], int model = 0) {
     R w = (R)q.x, x = (R)q.y, y = (R)q.z, z = (R)q.w;
     V3<R> c0 = {R(1) - R(2) * (y * y + z * z), R(2) * (x * y + w * z), R(2) * (x * z - w * y)};
     V3<R> c1 = {R(2) * (x * y - w * z), R(1) - R(2) * (x * x + z * z), R(2) * (y * z + w * x)};
     V3<R> c2 = {R(2) * (x * z + w * y), R(2) * (y * z - w * x), R(1) - R(2) * (x * x + y * y)};
+    if (model == 1) {
+        u[0] = c2;
+        u[1] = {-c2.x, -c2.y, -c2.z};
+        u[2] = u[3] = {R(0), R(0), R(0)};
+        return;
+    }
     const R k = R(0.57735026918962576451);  // 1/sqrt(3)
     u[0] = {k * (c0.x + c1.x + c2.x), k * (c0.y + c1.y + c2.y), k * (c0.z + c1.z + c2.z)};
     u[1] = {k * (c0.x - c1.x - c2.x), k * (c0.y - c1.y - c2.y), k * (c0.z - c1.z - c2.z)};
@@ -161,6 +169,64 @@ __device__ __forceinline__ void patch_dirs(const double4& q, V3<R> u[4]) {
 
 __device__ __forceinline__ float exp_r(float a) { return __expf(a); }
 __device__ __forceinline__ double exp_r(double a) { return exp(a); }
+
+// Two-patch pair (the model of Eqs. 2-4 with M = 2 polar patches): the core
+// (sigma/r)^200 plus, for each of the four patch pairs (a, b) with
+// s = |d + delta (u_j^b - u_i^a)| below rpc, -eps_p exp(-(s/w)^10 / 2).
+// d, r2, outputs and torques as for patchy_pair below.  The core (steep: its
+// force changes by 200 ulp per ulp of r^2) and the geometry are FP64 in every
+// precision; R is the type of the scalar factor of each patch term.
+template <typename R>
+__device__ __forceinline__ void patchy2_pair(const V3<double>& d, double r2, const V3<double> ui[4],
+                                             const V3<double> uj[4], const Sys& s, V3<double>& fj,
+                                             V3<double>& ti, V3<double>& tj, double& v) {
+    const PatchyC<double>& c = s.p64;
+    {   // (sigma^2/r^2)^100 by squaring; F_j = -dV/dr = 200 V_core d / r^2
+        const double inv = 1.0 / r2;
+        const double t = c.sig2 * inv;
+        const double t2 = t * t, t4 = t2 * t2, t8 = t4 * t4, t16 = t8 * t8, t32 = t16 * t16;
+        const double vc = (t32 * t32) * (t32 * t4);
+        v += vc;
+        const double fr = 200.0 * vc * inv;
+        fj.x += fr * d.x;
+        fj.y += fr * d.y;
+        fj.z += fr * d.z;
+    }
+    const R inv_w2 = (R)c.inv_w2, eps_p = (R)c.eps_p;
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            V3<double> dd64 = {d.x + c.delta * (uj[b].x - ui[a].x),
+                               d.y + c.delta * (uj[b].y - ui[a].y),
+                               d.z + c.delta * (uj[b].z - ui[a].z)};
+            double s2 = dot3(dd64, dd64);
+            if (c.rpc2 > 0.0 && !(s2 < c.rpc2)) continue;
+            // the exponent reaches (0.18 / 0.12)^10 / 2 = 29 at the patch range,
+            // so it is formed in FP64: its rounding error is the relative
+            // error of the term
+            const double x = s2 * c.inv_w2;  // (s/w)^2
+            const double x4d = (x * x) * (x * x);
+            const R x4 = (R)x4d;
+            const R E = exp_r((R)(-0.5 * x4d * x));
+            v -= (double)(eps_p * E);
+            // dV/dd_ab = kk d_ab; -dV/du_i^a = delta kk d_ab = dV/du_j^b.  Only
+            // the scalars are in R: the directions stay FP64, so the rounding
+            // of a bonded pair's torque is relative to the torque itself.
+            const double kk = (double)(R(5) * eps_p * E * x4 * inv_w2);
+            const double m = c.delta * kk;
+            fj.x -= kk * dd64.x;
+            fj.y -= kk * dd64.y;
+            fj.z -= kk * dd64.z;
+            ti.x += m * (ui[a].y * dd64.z - ui[a].z * dd64.y);
+            ti.y += m * (ui[a].z * dd64.x - ui[a].x * dd64.z);
+            ti.z += m * (ui[a].x * dd64.y - ui[a].y * dd64.x);
+            tj.x -= m * (uj[b].y * dd64.z - uj[b].z * dd64.y);
+            tj.y -= m * (uj[b].z * dd64.x - uj[b].x * dd64.z);
+            tj.z -= m * (uj[b].x * dd64.y - uj[b].y * dd64.x);
+        }
+    }
+}
 
 // Patchy pair: WCA core + sum over facing patch pairs of
 // -eps_p exp(-|d_ab|^2 / w^2) * A(c_i^a) * A(c_j^b), A(c) = c^2 for c > 0.
@@ -182,6 +248,10 @@ __device__ __forceinline__ void patchy_pair(const V3<double>& d, double r2, cons
     ti = {0, 0, 0};
     tj = {0, 0, 0};
     v = 0;
+    if (c.model == 1) {
+        patchy2_pair<R>(d, r2, ui, uj, s, fj, ti, tj, v);
+        return;
+    }
     if (r2 < c.wca2) {
         double inv = 1.0 / r2;
         double s2 = c.sig2 * inv;
@@ -1412,7 +1482,7 @@ __device__ __forceinline__ void b_vertex_patchy(const Sys& s, int bid, int nb) {
     if (i >= s.n) return;
     double4 xi = s.pos[i];
     V3<double> ui[4];
-    patch_dirs<double>(s.quat[i], ui);
+    patch_dirs<double>(s.quat[i], ui, s.p64.model);
     int cnt = s.ncount[i];
     Acc3<PREC> f, t;
     double e = 0, w = 0;
@@ -1427,7 +1497,7 @@ __device__ __forceinline__ void b_vertex_patchy(const Sys& s, int bid, int nb) {
         double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < s.rc2) {
             V3<double> uj[4];
-            patch_dirs<double>(s.quat[j], uj);
+            patch_dirs<double>(s.quat[j], uj, s.p64.model);
             V3<double> d = {dx, dy, dz};
             V3<double> fj, ti, tj;
             double v;
@@ -1547,8 +1617,8 @@ __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
                     }
                 } else {
                     V3<double> ui[4], uj[4];
-                    patch_dirs<double>(s.quat[i], ui);
-                    patch_dirs<double>(s.quat[j], uj);
+                    patch_dirs<double>(s.quat[i], ui, s.p64.model);
+                    patch_dirs<double>(s.quat[j], uj, s.p64.model);
                     V3<double> d = {dx, dy, dz};
                     V3<double> fj, ti, tj;
                     double v;
@@ -2135,7 +2205,7 @@ hipError_t launch_half_fill(const Sys& s, hipStream_t st) {
 }
 
 void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, double w,
-                   double delta, double rpc) {
+                   double delta, double rpc, int patch_model) {
     double s2 = sigma * sigma / (rc * rc);
     double s6 = s2 * s2 * s2;
     double vs = 4.0 * eps * (s6 * s6 - s6);
@@ -2144,9 +2214,11 @@ void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, do
              (float)vs};
     double wca2 = cbrt(2.0) * sigma * sigma;
     double rpc2 = rpc > 0 ? rpc * rpc : 0.0;
-    s.p64 = {sigma * sigma, 4.0 * eps, 24.0 * eps, eps, wca2, eps_p, 1.0 / (w * w), delta, rpc2};
+    s.p64 = {sigma * sigma, 4.0 * eps, 24.0 * eps, eps, wca2, eps_p, 1.0 / (w * w), delta, rpc2,
+             patch_model};
     s.p32 = {(float)(sigma * sigma), (float)(4.0 * eps), (float)(24.0 * eps), (float)eps,
-             (float)wca2, (float)eps_p, (float)(1.0 / (w * w)), (float)delta, (float)rpc2};
+             (float)wca2, (float)eps_p, (float)(1.0 / (w * w)), (float)delta, (float)rpc2,
+             patch_model};
 }
 
 template <int PREC>

@@ -45,6 +45,7 @@ class Workload:
     patch_delta: float = 0.5
     patch_rcut: float = 0.75
     inertia: float = 1.0
+    patch_model: str = "tetra"  # "tetra" (four patches) or "polar2" (the paper's two)
     max_neighbors: int = 0  # 0: choose from the density
 
     @property
@@ -78,6 +79,10 @@ WORKLOADS = {
     "lj_many": Workload("lj_many", "lj", 262144, 0.8, 1.5, 2.5, steps=1000),
     "lj_many_dense": Workload("lj_many_dense", "lj", 262144, 1.0, 1.5, 3.0, steps=1000),
     "patchy": Workload("patchy", "patchy", 131072, 0.5, 0.2, 1.5, steps=1000),
+    # the paper's patchy model: two polar patches, (sigma/r)^200 core, patch
+    # range 0.18 sigma, so r_c = 2 delta + 0.18 = 1.18; k_B T / eps = 0.15
+    "patchy_paper": Workload("patchy_paper", "patchy", 131072, 0.5, 0.15, 1.18, steps=1000,
+                             patch_rcut=0.18, patch_model="polar2"),
     "lj_precision": Workload("lj_precision", "lj", 1048576, 0.8, 1.0, 2.5, dt=0.005,
                              steps=10000),
 }
@@ -104,11 +109,30 @@ def lattice(n: int, box: float) -> np.ndarray:
     return (np.stack([ix, iy, iz], axis=1).astype(np.float64) + 0.5) * a
 
 
+def chain_columns(n: int, box: float, bond: float = 1.04):
+    """Sites on columns along z: each column holds nz = floor(box / bond)
+    sites spaced box / nz (>= bond), the columns sit on a square grid in
+    (x, y) filled one column at a time."""
+    nz = max(int(box // bond), 1)
+    ncol = -(-n // nz)
+    m = int(math.ceil(math.sqrt(ncol)))
+    a, b = box / m, box / nz
+    k = np.arange(n)
+    c, iz = k // nz, k % nz
+    return np.stack([(c % m + 0.5) * a, (c // m + 0.5) * a, (iz + 0.5) * b], axis=1)
+
+
 def make_state(w: Workload, seed: int, attempt: int = 0) -> State:
     rng = np.random.default_rng(seed + 1000 * attempt)
     L = w.box
     n = w.n
-    x = lattice(n, L) + rng.uniform(-0.05, 0.05, size=(n, 3)) * w.sigma
+    if w.patch_model == "polar2":
+        # chains along z with the patch axes mostly along the chain, so that
+        # about half the neighbouring patches are bonded (a stand-in for the
+        # chain fluid the two-patch model forms at k_B T = 0.15)
+        x = chain_columns(n, L) + rng.uniform(-0.02, 0.02, size=(n, 3)) * w.sigma
+    else:
+        x = lattice(n, L) + rng.uniform(-0.05, 0.05, size=(n, 3)) * w.sigma
     x = np.mod(x, L)
     x[x >= L] -= L
     v = rng.normal(0.0, math.sqrt(w.temp / w.mass), size=(n, 3))
@@ -121,6 +145,15 @@ def make_state(w: Workload, seed: int, attempt: int = 0) -> State:
         q = rng.normal(size=(n, 4))
         q /= np.linalg.norm(q, axis=1, keepdims=True)
         am = rng.normal(0.0, math.sqrt(w.inertia * w.temp), size=(n, 3))
+        if w.patch_model == "polar2":
+            # 70 %: body z along the lab z axis, tilted by an angle N(0, 0.15)
+            # about a random axis in the xy plane: q = (cos h, sin h ax, sin h ay, 0)
+            aligned = rng.random(n) < 0.7
+            h = 0.5 * rng.normal(0.0, 0.15, size=n)
+            phi = rng.uniform(0.0, 2.0 * math.pi, size=n)
+            qa = np.stack([np.cos(h), np.sin(h) * np.cos(phi), np.sin(h) * np.sin(phi),
+                           np.zeros(n)], axis=1)
+            q[aligned] = qa[aligned]
     return State(x=x, v=v, q=q, angmom=am, box=L, seed=seed, attempt=attempt)
 
 

@@ -39,7 +39,7 @@ class MDParams(ctypes.Structure):
                 ("patch_delta", ctypes.c_double), ("patch_rcut", ctypes.c_double),
                 ("inertia", ctypes.c_double), ("newton_m", ctypes.c_int32),
                 ("edge_store", ctypes.c_int32), ("cell_order", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("patch_model", ctypes.c_int32)]
 
 
 class MDSizes(ctypes.Structure):
@@ -129,6 +129,7 @@ def _dp(a):
 
 
 CELL_ORDER = {"row_major": 0, "row_major_gather": 1, "morton": 2, "hilbert": 3}
+PATCH_MODEL = {"tetra": 0, "polar2": 1}
 
 
 def make_params(w, prec: str = "fp64", newton_m: int = 0, edge_store: bool = False,
@@ -147,6 +148,7 @@ def make_params(w, prec: str = "fp64", newton_m: int = 0, edge_store: bool = Fal
     p.mass, p.dt = w.mass, w.dt
     p.eps_p, p.patch_w, p.patch_delta = w.eps_p, w.patch_w, w.patch_delta
     p.patch_rcut, p.inertia = w.patch_rcut, w.inertia
+    p.patch_model = PATCH_MODEL[w.patch_model] if w.pot == "patchy" else 0
     return p
 
 

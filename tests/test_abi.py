@@ -71,7 +71,7 @@ def test_edge_store_workspace(md):
     ("rcut", 0.0, -1), ("max_neighbors", 0, -1), ("mass", -1.0, -1), ("pot", 7, -1),
     ("prec", 9, -1), ("box", float("nan"), -1), ("newton_m", -1, -1), ("newton_m", 65, -1),
     ("edge_store", 2, -1), ("edge_store", -1, -1), ("cell_order", 4, -1), ("cell_order", -1, -1),
-    ("reserved", 1, -1),
+    ("patch_model", 1, -1), ("patch_model", 2, -1), ("patch_model", -1, -1),
 ])
 def test_invalid_params_rejected_on_host(md, field, value, status):
     p = _params(md, **{field: value})
@@ -82,6 +82,17 @@ def test_invalid_params_rejected_on_host(md, field, value, status):
     assert md.lib().md_create(ctypes.byref(p), 256, 1 << 40, 512, 1 << 40, None,
                               ctypes.byref(h)) == status
     assert not h.value
+
+
+def test_patch_models(md):
+    """Both patch models are accepted for patchy particles; a third is not."""
+    from paper_1401_4350_amd.inputs import WORKLOADS
+    s = md.MDSizes()
+    for name, model, status in (("patchy", 0, 0), ("patchy_paper", 1, 0), ("patchy", 2, -1)):
+        p = md.make_params(WORKLOADS[name].with_(n=4000))
+        assert p.patch_model == (model if status == 0 else 0)
+        p.patch_model = model
+        assert md.lib().md_query_sizes(ctypes.byref(p), ctypes.byref(s)) == status
 
 
 def test_buffer_checks_before_hip(md):
