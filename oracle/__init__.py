@@ -85,6 +85,11 @@ def lib():
         L.or_patchy_forces.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double,
                                        ctypes.POINTER(PatchyParams), ctypes.c_int, _D, _D, _D, _D,
                                        _D, _D]
+        _U64P = ctypes.POINTER(ctypes.c_uint64)
+        L.or_philox4x64.argtypes = [_U64P, _U64P, _U64P]
+        L.or_thermostat.restype = ctypes.c_int
+        L.or_thermostat.argtypes = [ctypes.c_int, _D, _D] + [ctypes.c_double] * 4 + \
+            [ctypes.c_uint64, ctypes.c_uint64]
         L.or_run.restype = ctypes.c_int
         L.or_run.argtypes = [ctypes.c_int, _D, _D, _D, _D, ctypes.c_double,
                              ctypes.POINTER(RunParams), ctypes.c_int, _D, _I, ctypes.c_int, _D]
@@ -266,3 +271,25 @@ def run(x, v, L, *, pot, nsteps, dt, skin, mass=1.0, inertia=1.0, lj: LJ | None 
         out["q"] = qq
         out["angmom"] = am
     return out
+
+
+def philox4x64(ctr, key):
+    """Philox4x64-10 block: four uint64 words from a 4-word counter and a
+    2-word key."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    kk = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    P = ctypes.POINTER(ctypes.c_uint64)
+    lib().or_philox4x64(c.ctypes.data_as(P), kk.ctypes.data_as(P), out.ctypes.data_as(P))
+    return out
+
+
+def thermostat(v, angmom, T, prob, seed, counter, mass=1.0, inertia=1.0):
+    """(v', angmom', refreshed) after one thermostat application (or_thermostat);
+    the inputs are not modified.  angmom may be None."""
+    v2 = np.array(v, dtype=np.float64, order="C", copy=True)
+    a2 = None if angmom is None else np.array(angmom, dtype=np.float64, order="C", copy=True)
+    n = v2.shape[0]
+    hits = lib().or_thermostat(n, _d(v2), _d(a2) if a2 is not None else None, T, mass, inertia,
+                               prob, seed, counter)
+    return v2, a2, hits

@@ -663,3 +663,75 @@ int or_run(int n, double* x, double* v, double* q, double* angmom, double L,
     free(xb);
     return nrb;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Stochastic thermostat                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* 64 x 64 -> 128-bit product, high and low words. */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t* hi, uint64_t* lo) {
+    unsigned __int128 p = (unsigned __int128)a * b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    /* multipliers of the S-box and the Weyl increments of the key schedule */
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) { /* the key advances between rounds */
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t h0, l0, h1, l1;
+        mulhilo64(M0, x0, &h0, &l0);
+        mulhilo64(M1, x2, &h1, &l1);
+        uint64_t y0 = h1 ^ x1 ^ k0, y1 = l1, y2 = h0 ^ x3 ^ k1, y3 = l0;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+    }
+    out[0] = x0;
+    out[1] = x1;
+    out[2] = x2;
+    out[3] = x3;
+}
+
+/* uniform on (0, 1) from the top 53 bits */
+static double unit53(uint64_t r) { return ((double)(r >> 11) + 0.5) * 0x1.0p-53; }
+
+/* Box-Muller: two standard normals from two words */
+static void box_muller(uint64_t a, uint64_t b, double* g0, double* g1) {
+    const double two_pi = 6.283185307179586476925286766559;
+    double rad = sqrt(-2.0 * log(unit53(a)));
+    double ang = two_pi * unit53(b);
+    *g0 = rad * cos(ang);
+    *g1 = rad * sin(ang);
+}
+
+int or_thermostat(int n, double* v, double* angmom, double T, double mass, double inertia,
+                  double prob, uint64_t seed, uint64_t counter) {
+    int hits = 0;
+    const uint64_t key[2] = {seed, 0};
+    for (int i = 0; i < n; i++) {
+        uint64_t ca[4] = {(uint64_t)i, counter, 0, 0}, cb[4] = {(uint64_t)i, counter, 1, 0};
+        uint64_t A[4], B[4];
+        or_philox4x64(ca, key, A);
+        if (!(unit53(A[0]) < prob)) continue;
+        or_philox4x64(cb, key, B);
+        double g[6];
+        box_muller(A[1], A[2], &g[0], &g[1]);
+        box_muller(A[3], B[0], &g[2], &g[3]);
+        box_muller(B[1], B[2], &g[4], &g[5]);
+        double sv = sqrt(T / mass), sl = sqrt(inertia * T);
+        for (int c = 0; c < 3; c++) v[3 * i + c] = sv * g[c];
+        if (angmom)
+            for (int c = 0; c < 3; c++) angmom[3 * i + c] = sl * g[3 + c];
+        hits++;
+    }
+    return hits;
+}

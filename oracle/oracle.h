@@ -130,6 +130,28 @@ int or_run(int n, double* x, double* v, double* q, double* angmom, double L,
            const or_run_params* p, int nsteps, double* energies,
            int32_t* rebuild_steps, int rb_cap, double* disp_margin);
 
+/* ------------------------------------------------------------------------- */
+/* Stochastic thermostat                                                       */
+/* ------------------------------------------------------------------------- */
+
+/* Philox4x64-10, the counter-based generator of Salmon, Moraes, Dror and Shaw
+ * ("Parallel random numbers: as easy as 1, 2, 3", SC 2011): out = the ten
+ * keyed rounds applied to the 256-bit counter ctr under the 128-bit key. */
+void or_philox4x64(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
+
+/* One application of the NVT thermostat in the reading of the Methods section
+ * (the Brownian scheme it cites: every so many steps, each particle's momenta
+ * are redrawn from the Maxwell-Boltzmann distribution at temperature T with
+ * probability prob).  Particle i (its index in x, v) draws two Philox blocks,
+ * A = philox({i, counter, 0, 0}, {seed, 0}) and B = philox({i, counter, 1, 0},
+ * {seed, 0}); u(r) = ((r >> 11) + 1/2) 2^-53.  It is refreshed when
+ * u(A0) < prob, with Box-Muller normals g(a, b) = sqrt(-2 ln u(a))
+ * (cos 2 pi u(b), sin 2 pi u(b)) taken in the order g(A1, A2), g(A3, B0),
+ * g(B1, B2): the first three are v_i sqrt(m / T), the next three (patchy)
+ * L_i / sqrt(I T).  angmom may be NULL (LJ).  Returns the number refreshed. */
+int or_thermostat(int n, double* v, double* angmom, double T, double mass, double inertia,
+                  double prob, uint64_t seed, uint64_t counter);
+
 #ifdef __cplusplus
 }
 #endif
