@@ -158,18 +158,22 @@ def serving_bench(count, rate, steps, max_systems=64):
     return out
 
 
-def crossover_bench(torch, steps=100, warmup=20):
-    """Vertex against edge over system size and density, for both potentials:
+def crossover_bench(torch, steps=100, warmup=20, which=("lj", "patchy", "patchy_paper")):
+    """Vertex against edge over system size and density, for each potential:
     per point the MD step and the force pass of each decomposition (FP64).
     Sizes N = 2^10 .. 2^20 at each potential's own density (LJ 0.8, patchy
-    0.5), and densities 0.1, 0.3, 0.5, 0.8 at N = 2^17."""
+    0.5), and densities 0.1, 0.3, 0.5, 0.8 at N = 2^17 (0.1, 0.3, 0.5, the
+    paper's, for its two-patch model)."""
     from paper_1401_4350_amd import md
     from paper_1401_4350_amd.inputs import WORKLOADS, make_state
     points = []
-    for pot, base in (("lj", "lj_many"), ("patchy", "patchy")):
+    for pot, base in (("lj", "lj_many"), ("patchy", "patchy"), ("patchy_paper", "patchy_paper")):
+        if pot not in which:
+            continue
         b = WORKLOADS[base]
         grid = [(2 ** e, b.rho) for e in range(10, 21, 2)]
-        grid += [(2 ** 17, r) for r in (0.1, 0.3, 0.5, 0.8)]
+        dens = (0.1, 0.3, 0.5) if pot == "patchy_paper" else (0.1, 0.3, 0.5, 0.8)
+        grid += [(2 ** 17, r) for r in dens]
         for n, rho in grid:
             w = b.with_(n=n, rho=rho)
             if w.box <= 2 * w.rv:
@@ -266,6 +270,8 @@ def main():
     ap.add_argument("--serving-steps", type=int, default=1000)
     ap.add_argument("--crossover", action="store_true",
                     help="print the vertex/edge crossover sweep instead of the headline line")
+    ap.add_argument("--crossover-pots", default="lj,patchy,patchy_paper",
+                    help="potentials of the crossover sweep (comma-separated)")
     ap.add_argument("--locality", action="store_true",
                     help="cell orders (row-major staged / gathered, Morton, Hilbert) instead of the bench line")
     ap.add_argument("--drift", action="store_true",
@@ -286,7 +292,8 @@ def main():
 
     torch.cuda.set_device(0)
     if args.crossover:
-        print(json.dumps({"crossover": crossover_bench(torch)}), flush=True)
+        pots = tuple(args.crossover_pots.split(","))
+        print(json.dumps({"crossover": crossover_bench(torch, which=pots)}), flush=True)
         return
     if args.drift:
         print(json.dumps({"drift": drift_bench(torch)}), flush=True)

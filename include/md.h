@@ -205,6 +205,22 @@ md_status md_forces(md_system* s, int32_t mode);
  * if they are not valid.  Syncs at the end and reports device errors. */
 md_status md_step(md_system* s, int32_t nsteps, int32_t mode);
 
+/* The NVT thermostat of the Methods section, in the reading of the Brownian
+ * scheme it cites: every particle's momenta are redrawn, with probability
+ * prob, from the Maxwell-Boltzmann distribution at `temperature` (v_c normal
+ * with variance T / m; for patchy particles also L_c, variance I T).  Call it
+ * between md_step calls, every so many steps.  Random numbers: Philox4x64-10
+ * (Salmon et al., SC 2011) with key (seed, 0) and counter (i, counter, b, 0),
+ * i the particle's index in the caller's order, b = 0, 1 the block;
+ * u(r) = ((r >> 11) + 1/2) 2^-53.  Particle i is drawn when u(A0) < prob;
+ * Box-Muller pairs sqrt(-2 ln u(a)) (cos 2 pi u(b), sin 2 pi u(b)) from
+ * (A1, A2), (A3, B0), (B1, B2) give v_x, v_y, v_z, then L_x, L_y, L_z.  The
+ * same (seed, counter) gives the same draws; use a new counter per call.
+ * Positions and forces are unchanged.  Errors: temperature < 0 or not finite,
+ * prob outside [0, 1], no state.  Async. */
+md_status md_thermostat(md_system* s, double temperature, double prob, uint64_t seed,
+                        uint64_t counter);
+
 /* Kinetic energy (translational + rotational), potential energy
  * sum_{i<j} V_ij and virial sum_{i<j} r_ij . F_j, reduced in FP64 in a fixed
  * order (deterministic for a given particle order).  Any output may be NULL.

@@ -632,6 +632,19 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     return MD_OK;
 }
 
+md_status md_thermostat(md_system* s, double temperature, double prob, uint64_t seed,
+                        uint64_t counter) {
+    if (!s) return MD_ERR_INVALID_ARG;
+    if (s->batch) return s->admitted();
+    if (!std::isfinite(temperature) || !(temperature >= 0) || !(prob >= 0) || !(prob <= 1))
+        return s->fail(MD_ERR_INVALID_ARG, "thermostat needs temperature >= 0 and 0 <= prob <= 1");
+    if (!s->state_set) return s->fail(MD_ERR_STATE, "md_set_state first");
+    const double sv = std::sqrt(temperature / s->p.mass);
+    const double sl = s->p.pot == MD_POT_PATCHY ? std::sqrt(s->p.inertia * temperature) : 0.0;
+    return s->hip(md::launch_thermostat(s->sys, sv, sl, prob, seed, counter, s->stream),
+                  "thermostat");
+}
+
 md_status md_profile_enable(md_system* s, int32_t on) {
     if (!s) return MD_ERR_INVALID_ARG;
     if (s->batch) return s->admitted();

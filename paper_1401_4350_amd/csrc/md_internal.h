@@ -234,6 +234,10 @@ hipError_t launch_kick(const Sys& s, hipStream_t st);
 hipError_t launch_energy(const Sys& s, int prec, hipStream_t st);
 hipError_t launch_clear_rebuild(const Sys& s, hipStream_t st);
 
+// Momentum refresh of the NVT thermostat (sv = sqrt(T / m), sl = sqrt(I T)).
+hipError_t launch_thermostat(const Sys& s, double sv, double sl, double prob, uint64_t seed,
+                             uint64_t counter, hipStream_t st);
+
 // Fills the potential constants of s from the physical parameters.
 void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, double w,
                    double delta, double rpc, int patch_model);

@@ -423,13 +423,13 @@ __device__ __forceinline__ long long block_scan(int len, Load load, Emit emit) {
     return base;
 }
 
-// Exclusive scan of the cell counts into cell_start by one workgroup; the
-// counts are cleared for the next build.
+// Exclusive scan of the cell counts into cell_start by one workgroup (the
+// scatter pass clears the counts for the next build).
 __device__ __forceinline__ void scan_cells(const Sys& s) {
-    // the counts come from atomics; reading them by exchange also clears
-    // them for the next build
+    // the counts come from other workgroups' atomics: device-coherent loads
+    // (a read-and-clear exchange per cell costs an atomic round trip each)
     const long long tot = block_scan<32>(
-        s.ncell, [&](int k) { return atomicExch(&s.ccount[k], 0); },
+        s.ncell, [&](int k) { return coh_load(&s.ccount[k]); },
         [&](int k, long long run, int) { s.cstart[k] = (int)run; });
     if (threadIdx.x == 0) s.cstart[s.ncell] = (int)tot;
 }
@@ -479,6 +479,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_bin(Sys s) { b_cell_bin(s, bloc
 __device__ __forceinline__ void b_cell_scatter(const Sys& s, int bid, int nb) {
     if (!s.ctrl->rebuild) return;
     int p = bid * kBlock + threadIdx.x;
+    // the scan has read the counts: clear them for the next build
+    for (int c = p; c < s.ncell; c += nb * kBlock) s.ccount[c] = 0;
     if (p >= s.n) return;
     s.order[s.cstart[s.cell[p]] + s.rank[p]] = p;
 }
@@ -2353,6 +2355,74 @@ hipError_t launch_kick(const Sys& s, hipStream_t st) {
 // Energy pass: per-particle potential energy and virial (vertex walk in the
 // configured precision, forces rewritten identically), kinetic terms, and the
 // fixed-order reduction into s.red[3 * kRedBlocks + {0,1,2}].
+// ---------------------------------------------------------------------------
+// NVT thermostat: each particle's momenta are redrawn from the
+// Maxwell-Boltzmann distribution with probability prob (Methods section, the
+// Brownian scheme it cites).  Random numbers come from Philox4x64-10 (Salmon,
+// Moraes, Dror and Shaw, SC 2011) keyed by (seed, 0), counter (particle id,
+// call counter, block, 0), so a particle's draws follow it through every
+// re-sort of the slots.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void philox4x64_10(uint64_t x[4], uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t h0 = __umul64hi(M0, x[0]), l0 = M0 * x[0];
+        const uint64_t h1 = __umul64hi(M1, x[2]), l1 = M1 * x[2];
+        const uint64_t y0 = h1 ^ x[1] ^ k0, y2 = h0 ^ x[3] ^ k1;
+        x[0] = y0;
+        x[1] = l1;
+        x[2] = y2;
+        x[3] = l0;
+    }
+}
+
+// (0, 1) from the top 53 bits
+__device__ __forceinline__ double unit53(uint64_t r) {
+    return ((double)(r >> 11) + 0.5) * 0x1.0p-53;
+}
+
+// two standard normals (Box-Muller) from two words
+__device__ __forceinline__ void box_muller(uint64_t a, uint64_t b, double& g0, double& g1) {
+    const double rad = sqrt(-2.0 * log(unit53(a)));
+    const double ang = 6.283185307179586476925286766559 * unit53(b);
+    g0 = rad * cos(ang);
+    g1 = rad * sin(ang);
+}
+
+// One lane per slot.  sv = sqrt(T / m), sl = sqrt(I T).  Draws: block A's
+// first word decides; normals from (A1, A2), (A3, B0), (B1, B2) give v, then L.
+__global__ __launch_bounds__(kBlock) void k_thermostat(Sys s, double sv, double sl, double prob,
+                                                       uint64_t seed, uint64_t counter) {
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= s.n) return;
+    const uint64_t id = (uint64_t)s.id[q];
+    uint64_t A[4] = {id, counter, 0, 0};
+    philox4x64_10(A, seed, 0);
+    if (!(unit53(A[0]) < prob)) return;
+    uint64_t B[4] = {id, counter, 1, 0};
+    philox4x64_10(B, seed, 0);
+    double g[6];
+    box_muller(A[1], A[2], g[0], g[1]);
+    box_muller(A[3], B[0], g[2], g[3]);
+    box_muller(B[1], B[2], g[4], g[5]);
+    s.vel[q] = make_double4(sv * g[0], sv * g[1], sv * g[2], 0.0);
+    if (s.pot == 1) s.angm[q] = make_double4(sl * g[3], sl * g[4], sl * g[5], 0.0);
+}
+
+hipError_t launch_thermostat(const Sys& s, double sv, double sl, double prob, uint64_t seed,
+                             uint64_t counter, hipStream_t st) {
+    hipLaunchKernelGGL(k_thermostat, grid_n(s.n), dim3(kBlock), 0, st, s, sv, sl, prob, seed,
+                       counter);
+    return hipGetLastError();
+}
+
 hipError_t launch_energy(const Sys& s, int prec, hipStream_t st) {
     if (prec == 0) vertex_dispatch<0>(s, false, true, st);
     else if (prec == 1) vertex_dispatch<1>(s, false, true, st);

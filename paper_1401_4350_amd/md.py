@@ -90,6 +90,8 @@ _SIGS = {
     "md_step": ([_sys_p, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "md_energy": ([_sys_p, _D, _D, _D], ctypes.c_int),
     "md_particle_energies": ([_sys_p, _D], ctypes.c_int),
+    "md_thermostat": ([_sys_p, ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
+                       ctypes.c_uint64], ctypes.c_int),
     "md_get_state": ([_sys_p, _D, _D, _D, _D, _D, _D], ctypes.c_int),
     "md_get_pairs": ([_sys_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
                       ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -237,6 +239,11 @@ class System:
 
     def step(self, nsteps: int, mode: str = "vertex"):
         self._check(_lib.md_step(self._h, nsteps, MODE[mode]), "md_step")
+
+    def thermostat(self, temperature: float, prob: float, seed: int, counter: int):
+        """md_thermostat: redraw momenta with probability prob at temperature."""
+        self._check(_lib.md_thermostat(self._h, temperature, prob, seed, counter),
+                    "md_thermostat")
 
     def energy(self):
         k, p, w = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -1,0 +1,134 @@
+"""GPU parity, NVT thermostat (md_thermostat through the C ABI) against the
+oracle's: the same particles are drawn (bit-exact decision) and their new
+momenta agree to rounding of the math library (1e-13 relative); the others
+keep theirs bit for bit.  Then thermostatted trajectories against the oracle,
+and the temperature a full refresh sets."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_4350_amd.inputs import WORKLOADS
+
+from _helpers import accepted_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def md():
+    from paper_1401_4350_amd import md as m
+    return m
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_system(md, w, s, prec="fp64"):
+    g = md.System(md.make_params(w, prec))
+    g.set_state(s.x, s.v, s.q, s.angmom)
+    g.build()
+    return g
+
+
+def check_refresh(before, after, ref):
+    changed = np.any(ref != before, axis=1)
+    assert np.array_equal(np.any(after != before, axis=1), changed)
+    assert np.array_equal(after[~changed], before[~changed])
+    np.testing.assert_allclose(after[changed], ref[changed], rtol=1e-13, atol=1e-15)
+    return int(changed.sum())
+
+
+@pytest.mark.parametrize("name,over", [
+    ("lj_small", {}),
+    ("lj_small", {"n": 1001}),
+    ("patchy_paper", {"n": 3000}),
+    ("patchy", {"n": 2000}),
+    ("lj_many", {}),
+])
+@pytest.mark.parametrize("prob", [0.0, 0.05, 1.0])
+def test_refresh_equals_oracle(md, name, over, prob):
+    w = WORKLOADS[name].with_(**over)
+    s = accepted_state(w, 1)
+    say(f"[thermostat] {name} {over} p={prob}")
+    g = gpu_system(md, w, s)
+    g.step(20, "vertex")  # slots re-sorted, momenta moved on
+    st0 = g.get_state()
+    g.thermostat(w.temp, prob, 77, 3)
+    st1 = g.get_state()
+    patchy = w.pot == "patchy"
+    rv, rl, hits = oracle.thermostat(st0["v"], st0["angmom"] if patchy else None, w.temp, prob,
+                                     seed=77, counter=3, mass=w.mass, inertia=w.inertia)
+    assert check_refresh(st0["v"], st1["v"], rv) == hits
+    if patchy:
+        assert check_refresh(st0["angmom"], st1["angmom"], rl) == hits
+    if prob == 0.0:
+        assert hits == 0
+    if prob == 1.0:
+        assert hits == w.n
+    for key in ("x", "f"):
+        assert np.array_equal(st1[key], st0[key])
+
+
+@pytest.mark.parametrize("name,mode", [("lj_small", "vertex"), ("patchy_paper", "edge"),
+                                       ("patchy_paper", "vertex")])
+def test_nvt_trajectory(md, name, mode):
+    """Three blocks of 40 steps with a thermostat call after each, against the
+    oracle doing the same."""
+    w = WORKLOADS[name].with_(n=2000)
+    s = accepted_state(w, 4)
+    say(f"[thermostat trajectory] {name} {mode}")
+    patchy = w.pot == "patchy"
+    pp = None
+    if patchy:
+        pp = oracle.Patchy(eps=w.eps, sigma=w.sigma, rcut=w.rcut, eps_p=w.eps_p, w=w.patch_w,
+                           delta=w.patch_delta, rpc=w.patch_rcut, model=1)
+    g = gpu_system(md, w, s)
+    x, v, q, L = s.x, s.v, s.q, s.angmom
+    for blk in range(3):
+        kw = dict(pot=w.pot, nsteps=40, dt=w.dt, skin=w.skin)
+        if patchy:
+            ref = oracle.run(x, v, s.box, patchy=pp, q=q, angmom=L, inertia=w.inertia, **kw)
+        else:
+            ref = oracle.run(x, v, s.box, lj=oracle.LJ(w.eps, w.sigma, w.rcut), **kw)
+        g.step(40, mode)
+        g.thermostat(w.temp, 0.2, 5, blk)
+        x, q = ref["x"], ref.get("q")
+        v, L, _ = oracle.thermostat(ref["v"], ref.get("angmom"), w.temp, 0.2, seed=5, counter=blk,
+                                    mass=w.mass, inertia=w.inertia)
+        out = g.get_state()
+        d = out["x"] - x
+        d -= s.box * np.rint(d / s.box)
+        assert np.abs(d).max() < 1e-9, blk
+        assert np.abs(out["v"] - v).max() < 1e-9, blk
+        if patchy:
+            assert np.abs(out["angmom"] - L).max() < 1e-9, blk
+
+
+def test_full_refresh_sets_temperature(md):
+    """prob = 1 on 262 144 LJ particles: kinetic energy per degree of freedom
+    within 5 standard deviations of T / 2."""
+    w = WORKLOADS["lj_many"]
+    s = accepted_state(w, 2)
+    say("[thermostat temperature] lj_many")
+    g = gpu_system(md, w, s)
+    T = 0.7
+    g.thermostat(T, 1.0, 123, 0)
+    ke, _, _ = g.energy()
+    dof = 3 * w.n
+    t_meas = 2 * ke / dof
+    assert abs(t_meas - T) < 5 * T * math.sqrt(2.0 / dof)
+
+
+def test_invalid_arguments(md):
+    w = WORKLOADS["lj_small"].with_(n=500)
+    s = accepted_state(w, 1)
+    g = gpu_system(md, w, s)
+    for T, p in ((-1.0, 0.5), (float("nan"), 0.5), (1.0, -0.1), (1.0, 1.5)):
+        with pytest.raises(md.MDError) as ei:
+            g.thermostat(T, p, 1, 0)
+        assert ei.value.status == -1
