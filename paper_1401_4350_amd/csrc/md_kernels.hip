@@ -337,6 +337,7 @@ __global__ void k_clear_ctrl(Ctrl* c, int* sync) {
     c->npairs = 0;
     c->rebuilds = 0;
     c->half_stale = 0;
+    c->eidx_stale = 0;
 }
 
 // True in the one workgroup, of the nb that call this with the same counter,
