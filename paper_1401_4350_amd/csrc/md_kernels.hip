@@ -399,8 +399,13 @@ __device__ __forceinline__ long long block_scan(int len, Load load, Emit emit) {
     for (int c0 = 0; c0 < len; c0 += kBlock * V) {
         const int k0 = c0 + t * V;
         int v[V];
+        if (k0 + V <= len) {  // whole run in range: every load issued before any wait
 #pragma unroll
-        for (int u = 0; u < V; u++) v[u] = k0 + u < len ? load(k0 + u) : 0;
+            for (int u = 0; u < V; u++) v[u] = load(k0 + u);
+        } else {
+#pragma unroll
+            for (int u = 0; u < V; u++) v[u] = k0 + u < len ? load(k0 + u) : 0;
+        }
         long long sum = 0;
 #pragma unroll
         for (int u = 0; u < V; u++) sum += v[u];
@@ -425,14 +430,68 @@ __device__ __forceinline__ long long block_scan(int len, Load load, Emit emit) {
 }
 
 // Exclusive scan of the cell counts into cell_start by one workgroup (the
-// scatter pass clears the counts for the next build).
+// scatter pass clears the counts for the next build).  Sparse systems have
+// several cells per particle, so the counts are read and the starts written
+// coalesced (element c0 + u * kBlock + t by thread t), through an LDS tile in
+// which each thread scans kCellRun consecutive counts.  The counts come from
+// other workgroups' atomics: device-coherent loads.
+constexpr int kCellRun = 16;
+__device__ __forceinline__ int cell_lds(int p) { return p + p / 32; }  // pad: no bank conflicts
+
 __device__ __forceinline__ void scan_cells(const Sys& s) {
-    // the counts come from other workgroups' atomics: device-coherent loads
-    // (a read-and-clear exchange per cell costs an atomic round trip each)
-    const long long tot = block_scan<32>(
-        s.ncell, [&](int k) { return coh_load(&s.ccount[k]); },
-        [&](int k, long long run, int) { s.cstart[k] = (int)run; });
-    if (threadIdx.x == 0) s.cstart[s.ncell] = (int)tot;
+    __shared__ int tile[kBlock * kCellRun + kBlock * kCellRun / 32];
+    __shared__ long long part[kBlock];
+    const int t = threadIdx.x, len = s.ncell;
+    constexpr int C = kBlock * kCellRun;
+    long long base = 0;
+    for (int c0 = 0; c0 < len; c0 += C) {
+        int v[kCellRun];
+        if (c0 + C <= len) {
+#pragma unroll
+            for (int u = 0; u < kCellRun; u++) v[u] = coh_load(&s.ccount[c0 + u * kBlock + t]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < kCellRun; u++) {
+                const int k = c0 + u * kBlock + t;
+                v[u] = k < len ? coh_load(&s.ccount[k]) : 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCellRun; u++) tile[cell_lds(u * kBlock + t)] = v[u];
+        __syncthreads();
+        // thread t: counts t * kCellRun .. + kCellRun - 1 of the chunk
+        int run[kCellRun];
+        long long sum = 0;
+#pragma unroll
+        for (int u = 0; u < kCellRun; u++) {
+            run[u] = tile[cell_lds(t * kCellRun + u)];
+            sum += run[u];
+        }
+        part[t] = sum;
+        __syncthreads();
+        for (int off = 1; off < kBlock; off <<= 1) {
+            long long w = t >= off ? part[t - off] : 0;
+            __syncthreads();
+            part[t] += w;
+            __syncthreads();
+        }
+        long long r = base + part[t] - sum;
+#pragma unroll
+        for (int u = 0; u < kCellRun; u++) {
+            const int c = run[u];
+            tile[cell_lds(t * kCellRun + u)] = (int)r;
+            r += c;
+        }
+        base += part[kBlock - 1];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kCellRun; u++) {
+            const int k = c0 + u * kBlock + t;
+            if (k < len) s.cstart[k] = tile[cell_lds(u * kBlock + t)];
+        }
+        __syncthreads();  // the tile and part are rewritten by the next chunk
+    }
+    if (t == 0) s.cstart[len] = (int)base;
 }
 
 // Bins every particle into its cell (counts by atomics; the atomic's return
