@@ -32,10 +32,12 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stats_markdown(trace_csv: str, command: str, top: int = 40) -> str:
+def stats_markdown(trace_csv: str, command: str, top: int = 40,
+                   keep: tuple[str, ...] = ("k_vertex_lj",)) -> str:
     """Per (kernel, grid) statistics of a kernel trace: the same kernel
     launched on systems of different size is listed once per grid size, so
-    the headline launches can be told apart from the others."""
+    the headline launches can be told apart from the others.  The `top` rows
+    by total time, then every other row whose name contains one of `keep`."""
     agg: dict[tuple[str, int], list[float]] = {}
     for r in csv.DictReader(open(trace_csv)):
         key = (r["Kernel_Name"], int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"])))
@@ -44,7 +46,8 @@ def stats_markdown(trace_csv: str, command: str, top: int = 40) -> str:
     out = [f"Command: `{command}`", "",
            "| kernel | workgroups | calls | total ms | average us | min us | max us |",
            "|---|---:|---:|---:|---:|---:|---:|"]
-    for (name, wg), d in rows[:top]:
+    rows = rows[:top] + [r for r in rows[top:] if any(s in r[0][0] for s in keep)]
+    for (name, wg), d in rows:
         out.append(f"| `{name[:70]}` | {wg} | {len(d)} | {sum(d) / 1e3:.3f} | {sum(d) / len(d):.2f} "
                    f"| {min(d):.2f} | {max(d):.2f} |")
     return "\n".join(out) + "\n"

@@ -26,8 +26,8 @@ def say(msg):
     sys.stdout.flush()
 
 
-# (workload, overrides, precision, steps): LJ and patchy, dense and dilute,
-# small boxes (n_c = 3 and 4), FP64 and FP32 pair maths.
+# (workload, overrides, precision, steps): LJ and both patchy models, dense and
+# dilute, small boxes (n_c = 3 and 4), FP64 and FP32 pair maths.
 MIX = [
     ("lj_small", {"n": 3000, "rho": 0.8}, "fp64", 60),
     ("lj_small", {"n": 700, "rho": 0.9}, "fp64", 45),
@@ -35,6 +35,7 @@ MIX = [
     ("lj_small", {"n": 5000, "rho": 0.6}, "fp32", 64),
     ("patchy", {"n": 900, "rho": 0.4}, "fp32", 33),
     ("lj_small", {"n": 2000, "rho": 0.85}, "fp32_kahan", 20),
+    ("patchy_paper", {"n": 1200, "rho": 0.3}, "fp64", 40),  # the two-patch model
 ]
 
 
