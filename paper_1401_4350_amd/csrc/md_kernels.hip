@@ -1646,13 +1646,25 @@ __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
         const int rlast = (m + 1 < nchunks) ? s.chunk_row[m + 1] : s.n - 1;
         const long long e = m * kWave + lane;
         const bool valid = e < npairs;
-        // row of entry e: r0 plus the number of later row starts <= e
+        // row of entry e: the last row in [r0, rlast] whose start is <= e
         int row = r0;
-        for (int base = r0 + 1; base <= rlast; base += kWave) {
-            int rr = base + lane;
+        if (rlast - r0 <= kWave) {
+            // dense half list: one coalesced load of the chunk's row starts,
+            // counted through lane reads
+            int rr = r0 + 1 + lane;
             int hs = rr <= rlast ? s.hstart[rr] : INT_MAX;
-            int lim = min(kWave, rlast - base + 1);
+            int lim = rlast - r0;
             for (int q = 0; q < lim; q++) row += (__builtin_amdgcn_readlane(hs, q) <= e);
+        } else {
+            // sparse half list (a chunk spans many rows, most of them empty):
+            // binary search per lane
+            int lo = r0, hi = rlast;
+            while (lo < hi) {
+                const int mid = lo + (hi - lo + 1) / 2;
+                if ((long long)s.hstart[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            row = lo;
         }
         const int i = row;
         const int ent = valid ? s.hj[e] : i;

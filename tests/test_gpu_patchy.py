@@ -127,3 +127,31 @@ def test_patchy_vertex_equals_edge(md):
     b = g.get_state()
     assert cond_rel_err(b["f"], a["f"], FA) <= 1e-10
     assert cond_rel_err(b["torque"], a["torque"], TA) <= 1e-10
+
+
+@pytest.mark.parametrize("mode", ["edge", "edge_det"])
+def test_sparse_half_list(md, mode):
+    """A dilute random fluid (rho = 0.02, uniform positions, random
+    orientations): about one pair per four particles, so a 64-entry chunk of
+    the half list spans hundreds of rows -- the edge pass finds each entry's
+    row by binary search there."""
+    w = WORKLOADS["patchy"].with_(n=20000, rho=0.02)
+    rng = np.random.default_rng(5)
+    L = w.box
+    x = rng.uniform(0.0, L, size=(w.n, 3))
+    q = rng.normal(size=(w.n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    zero = np.zeros((w.n, 3))
+    assert oracle.pair_margin(x, L, [w.rcut, w.rv]) > 1e-9
+    say(f"[patchy sparse half list] {mode}")
+    g = md.System(md.make_params(w, "fp64", edge_store=(mode == "edge_det")))
+    g.set_state(x, zero, q, zero)
+    g.build()
+    st = g.stats()
+    assert 0 < st["pairs"] < w.n // 2
+    g.forces(mode)
+    out = g.get_state()
+    F, T, _, _, FA, TA = oracle.patchy_forces(x, q, L, patchy_params(w), with_abs=True)
+    assert np.count_nonzero(np.abs(T).sum(1)) > 100
+    assert cond_rel_err(out["f"], F, FA) <= 1e-10
+    assert cond_rel_err(out["torque"], T, TA) <= 1e-10
