@@ -109,6 +109,23 @@ def time_mode(md, torch, w, state, mode, prec, steps, warmup, newton_m=0, cell_o
                 energy_per_particle=(ke + pe) / w.n)
 
 
+def thermostat_us(md, torch, w, state, calls=200, prob=0.01):
+    """Average duration of one md_thermostat call (the NVT momentum refresh)
+    on the workload, timed over `calls` back-to-back calls."""
+    g = md.System(md.make_params(w, "fp64"))
+    g.set_state(state.x, state.v, state.q, state.angmom)
+    g.build()
+    g.thermostat(w.temp, prob, 1, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(calls):
+        g.thermostat(w.temp, prob, 1, c + 1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.close()
+    return 1e6 * dt / calls
+
+
 def cpu_baseline(w, state, pairs, budget_s=20.0):
     """The FP64 oracle (single-threaded C) on the same state: a few velocity-
     Verlet steps, scaled to pair evaluations per second."""
@@ -358,6 +375,8 @@ def main():
         modes[k] = summary(r, nbv)
     for m, r in newton.items():
         modes[f"newton_m{m}"] = summary(r, newton_pass_bytes(w.n, r["pairs"], m))
+    if not args.no_variants:
+        modes["thermostat_call_us"] = thermostat_us(md, torch, w, state)
     modes["edge_over_vertex_speedup"] = runs["vertex"]["ms_per_step"] / runs["edge"]["ms_per_step"]
 
     out = {
