@@ -33,7 +33,10 @@
  * Both read Verlet lists of radius r_v = r_c + r_s built with a cell algorithm
  * (Methods section), and are followed by an FP64 velocity-Verlet update
  * (Methods section: positions and momenta are integrated in double precision;
- * forces may be computed in single precision).
+ * forces may be computed in single precision).  The potentials are the
+ * Lennard-Jones fluid (Eq. 1) and patchy particles (Eqs. 2-4: the paper's
+ * two-patch model, or a four-patch variant; md_patch_model); md_thermostat
+ * adds the NVT momentum refresh the Methods section runs with.
  *
  * Conventions for every entry point:
  *   - Every function returns md_status; nothing aborts or throws across the ABI.
