@@ -1721,18 +1721,20 @@ __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
             }
             continue;
         }
-        const bool nz = (fx != 0.0) | (fy != 0.0) | (fz != 0.0) | (tix != 0.0) | (tiy != 0.0) |
-                        (tiz != 0.0) | (tjx != 0.0) | (tjy != 0.0) | (tjz != 0.0);
-        // j side: only non-zero pairs touch memory
-        if (nz) {
+        const bool fnz = (fx != 0.0) | (fy != 0.0) | (fz != 0.0);
+        const bool tjnz = (tjx != 0.0) | (tjy != 0.0) | (tjz != 0.0);
+        const bool nz = fnz | tjnz | (tix != 0.0) | (tiy != 0.0) | (tiz != 0.0);
+        // j side: only non-zero results touch memory (a pair inside the core
+        // range with no patch in reach has a force but no torques)
+        if (fnz) {
             unsafeAtomicAdd(F + 4 * (size_t)j + 0, fx);
             unsafeAtomicAdd(F + 4 * (size_t)j + 1, fy);
             unsafeAtomicAdd(F + 4 * (size_t)j + 2, fz);
-            if (POT == 1) {
-                unsafeAtomicAdd(T + 4 * (size_t)j + 0, tjx);
-                unsafeAtomicAdd(T + 4 * (size_t)j + 1, tjy);
-                unsafeAtomicAdd(T + 4 * (size_t)j + 2, tjz);
-            }
+        }
+        if (POT == 1 && tjnz) {
+            unsafeAtomicAdd(T + 4 * (size_t)j + 0, tjx);
+            unsafeAtomicAdd(T + 4 * (size_t)j + 1, tjy);
+            unsafeAtomicAdd(T + 4 * (size_t)j + 2, tjz);
         }
         // i side: combine the lanes of each row, skip all-zero rows
         const int key = valid ? i : s.n + lane;
@@ -1749,17 +1751,17 @@ __device__ __forceinline__ void b_edge(const Sys& s, int bid, int nb) {
             }
             int up = __shfl_up(key, 1);
             bool head = valid && (lane == 0 || up != key);
-            bool rnz = (sx != 0.0) | (sy != 0.0) | (sz != 0.0) | (ux != 0.0) | (uy != 0.0) |
-                       (uz != 0.0);
-            if (head && rnz) {
+            const bool rfnz = (sx != 0.0) | (sy != 0.0) | (sz != 0.0);
+            const bool rtnz = (ux != 0.0) | (uy != 0.0) | (uz != 0.0);
+            if (head && rfnz) {
                 unsafeAtomicAdd(F + 4 * (size_t)i + 0, sx);
                 unsafeAtomicAdd(F + 4 * (size_t)i + 1, sy);
                 unsafeAtomicAdd(F + 4 * (size_t)i + 2, sz);
-                if (POT == 1) {
-                    unsafeAtomicAdd(T + 4 * (size_t)i + 0, ux);
-                    unsafeAtomicAdd(T + 4 * (size_t)i + 1, uy);
-                    unsafeAtomicAdd(T + 4 * (size_t)i + 2, uz);
-                }
+            }
+            if (POT == 1 && head && rtnz) {
+                unsafeAtomicAdd(T + 4 * (size_t)i + 0, ux);
+                unsafeAtomicAdd(T + 4 * (size_t)i + 1, uy);
+                unsafeAtomicAdd(T + 4 * (size_t)i + 2, uz);
             }
         }
     }
