@@ -165,7 +165,7 @@ enum BatchClass {
     // few small-box systems with large regions do not lower the occupancy of
     // all the others.  A system's blocks go to the bucket of its region
     // capacity (lds_bucket); its count in the other two is zero.
-    kClsVertex0,       // vertex pass: LJ ntiles, patchy nblk
+    kClsVertex0,       // vertex pass: LJ ntiles; patchy ntiles or nblk (patchy_vertex_tpp)
     kClsVertex1,
     kClsVertex2,
     kClsEdge0,         // edge pass: LJ ntiles, patchy eblk
@@ -198,13 +198,23 @@ struct BatchDev {
 __host__ __device__ inline int sort_blocks(const Sys& s) { return s.nblk; }
 
 // Blocks a system takes in a class.
+// Lanes per particle of the patchy vertex pass: kTileTpp up to 65 536
+// particles, where one lane per particle leaves most of the chip idle; one
+// lane above, where the chip is full and the extra lanes only repeat work.
+constexpr int kPatchyLanesMaxN = 65536;
+__host__ __device__ inline int patchy_vertex_tpp(const Sys& s) {
+    return s.n <= kPatchyLanesMaxN ? kTileTpp : 1;
+}
+
 __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
     switch (cls) {
         case kClsParticle: return s.nblk;
         case kClsTile: return s.ntiles;
         case kClsSortTiles: return sort_blocks(s) + (s.ntiles + kBlock / kWave - 1) / (kBlock / kWave);
         case kClsVertex0: case kClsVertex1: case kClsVertex2:
-            return lds_bucket(s) == cls - kClsVertex0 ? (s.pot == 0 ? s.ntiles : s.nblk) : 0;
+            return lds_bucket(s) == cls - kClsVertex0
+                       ? (s.pot == 0 || patchy_vertex_tpp(s) > 1 ? s.ntiles : s.nblk)
+                       : 0;
         default:
             return lds_bucket(s) == cls - kClsEdge0 ? (s.pot == 0 ? s.ntiles : s.eblk) : 0;
     }

@@ -1535,21 +1535,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4))) 
     b_vertex_lj<PREC, TPP, KICK, ENERGY, DRIFT>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
-template <int PREC, bool KICK, bool ENERGY>
+template <int PREC, bool KICK, bool ENERGY, int TPP>
 __device__ __forceinline__ void b_vertex_patchy(const Sys& s, int bid, int nb) {
     using R = typename std::conditional<PREC == 0, double, float>::type;
-    int lb = bid;
-    int i = lb * kBlock + threadIdx.x;
+    // TPP lanes per particle: lane q takes list entries q, q + TPP, ...; the
+    // partial sums are then combined across the particle's lanes (a fixed
+    // order: deterministic).  Several lanes per particle pay where one lane
+    // per particle leaves the chip idle (small systems, patchy_vertex_tpp).
+    const int i = bid * (kBlock / TPP) + (int)threadIdx.x / TPP;
+    const int q = (int)threadIdx.x % TPP;
     if (KICK && bid == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
-    if (i >= s.n) return;
-    double4 xi = s.pos[i];
+    const bool act = i < s.n;
+    const int ii = act ? i : s.n - 1;
+    double4 xi = s.pos[ii];
     V3<double> ui[4];
-    patch_dirs<double>(s.quat[i], ui, s.p64.model);
-    int cnt = s.ncount[i];
+    patch_dirs<double>(s.quat[ii], ui, s.p64.model);
+    int cnt = act ? s.ncount[i] : 0;
     Acc3<PREC> f, t;
     double e = 0, w = 0;
-    const int* row = list_row(s, i);
-    for (int k = 0; k < cnt; k++) {
+    const int* row = list_row(s, ii);
+    for (int k = q; k < cnt; k += TPP) {
         int ent = row[list_off(k)];
         int j = entry_slot(ent);
         double4 xj = s.pos[j];
@@ -1574,6 +1579,20 @@ __device__ __forceinline__ void b_vertex_patchy(const Sys& s, int bid, int nb) {
     }
     double fx = f.gx(), fy = f.gy(), fz = f.gz();
     double tx = t.gx(), ty = t.gy(), tz = t.gz();
+#pragma unroll
+    for (int off = 1; off < TPP; off <<= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+        tx += __shfl_xor(tx, off);
+        ty += __shfl_xor(ty, off);
+        tz += __shfl_xor(tz, off);
+        if (ENERGY) {
+            e += __shfl_xor(e, off);
+            w += __shfl_xor(w, off);
+        }
+    }
+    if (!act || q != 0) return;
     if (ENERGY) {
         s.epart[i] = e;
         s.wpart[i] = w;
@@ -1596,8 +1615,10 @@ __device__ __forceinline__ void b_vertex_patchy(const Sys& s, int bid, int nb) {
     }
 }
 
-template <int PREC, bool KICK, bool ENERGY>
-__global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) { b_vertex_patchy<PREC, KICK, ENERGY>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x); }
+template <int PREC, bool KICK, bool ENERGY, int TPP>
+__global__ __launch_bounds__(kBlock) void k_vertex_patchy(Sys s) {
+    b_vertex_patchy<PREC, KICK, ENERGY, TPP>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
 
 // ---------------------------------------------------------------------------
 // Edge decomposition: one lane per half-list entry (pair i < j).  The lane
@@ -2300,7 +2321,7 @@ void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, do
 template <int PREC>
 static void vertex_dispatch(const Sys& s, bool kick, bool energy, hipStream_t st,
                             bool drift = false) {
-    dim3 g(s.nblk), b(kBlock);
+    dim3 b(kBlock);
     if (s.pot == 0) {
         constexpr int T = kTileTpp;
         dim3 gl((unsigned)s.ntiles);
@@ -2313,13 +2334,23 @@ static void vertex_dispatch(const Sys& s, bool kick, bool energy, hipStream_t st
             hipLaunchKernelGGL((k_vertex_lj<PREC, T, false, true>), gl, b, sh, st, s);
         else
             hipLaunchKernelGGL((k_vertex_lj<PREC, T, false, false>), gl, b, sh, st, s);
-    } else {
+    } else if (patchy_vertex_tpp(s) > 1) {
+        constexpr int T = kTileTpp;
+        dim3 gt((unsigned)s.ntiles);  // one tile of particles per workgroup
         if (kick)
-            hipLaunchKernelGGL((k_vertex_patchy<PREC, true, false>), g, b, 0, st, s);
+            hipLaunchKernelGGL((k_vertex_patchy<PREC, true, false, T>), gt, b, 0, st, s);
         else if (energy)
-            hipLaunchKernelGGL((k_vertex_patchy<PREC, false, true>), g, b, 0, st, s);
+            hipLaunchKernelGGL((k_vertex_patchy<PREC, false, true, T>), gt, b, 0, st, s);
         else
-            hipLaunchKernelGGL((k_vertex_patchy<PREC, false, false>), g, b, 0, st, s);
+            hipLaunchKernelGGL((k_vertex_patchy<PREC, false, false, T>), gt, b, 0, st, s);
+    } else {
+        dim3 g((unsigned)s.nblk);  // one lane per particle
+        if (kick)
+            hipLaunchKernelGGL((k_vertex_patchy<PREC, true, false, 1>), g, b, 0, st, s);
+        else if (energy)
+            hipLaunchKernelGGL((k_vertex_patchy<PREC, false, true, 1>), g, b, 0, st, s);
+        else
+            hipLaunchKernelGGL((k_vertex_patchy<PREC, false, false, 1>), g, b, 0, st, s);
     }
 }
 
@@ -2565,9 +2596,16 @@ __global__ __launch_bounds__(kBlock) void kb_vertex(BatchDev b, int step) {
             else if (s.prec == 1) b_vertex_lj<1, T, true, false>(s, lb, s.ntiles);
             else b_vertex_lj<2, T, true, false>(s, lb, s.ntiles);
         } else {
-            if (s.prec == 0) b_vertex_patchy<0, true, false>(s, lb, s.nblk);
-            else if (s.prec == 1) b_vertex_patchy<1, true, false>(s, lb, s.nblk);
-            else b_vertex_patchy<2, true, false>(s, lb, s.nblk);
+            const int nb = class_blocks(s, kClsVertex0 + lds_bucket(s));
+            if (patchy_vertex_tpp(s) > 1) {
+                if (s.prec == 0) b_vertex_patchy<0, true, false, T>(s, lb, nb);
+                else if (s.prec == 1) b_vertex_patchy<1, true, false, T>(s, lb, nb);
+                else b_vertex_patchy<2, true, false, T>(s, lb, nb);
+            } else {
+                if (s.prec == 0) b_vertex_patchy<0, true, false, 1>(s, lb, nb);
+                else if (s.prec == 1) b_vertex_patchy<1, true, false, 1>(s, lb, nb);
+                else b_vertex_patchy<2, true, false, 1>(s, lb, nb);
+            }
         }
     });
 }
