@@ -131,3 +131,19 @@ def test_full_size(md):
         out = g.get_state()
         assert cond_rel_err(out["f"], F, FA) <= 1e-10, mode
         assert cond_rel_err(out["torque"], T, TA) <= 1e-10, mode
+
+
+@pytest.mark.parametrize("n", [65536, 65537])
+def test_vertex_lane_count_boundary(md, n):
+    """The vertex pass runs four lanes per particle up to 65 536 particles and
+    one lane above: both sides of the switch against the oracle, with energies."""
+    w = WORKLOADS["patchy_paper"].with_(n=n)
+    s = accepted_state(w, 4)
+    say(f"[patchy_paper vertex lanes] n={n}")
+    g = gpu_system(md, w, s)
+    g.forces("vertex")
+    out = g.get_state()
+    F, T, e, _, FA, TA = oracle.patchy_forces(s.x, s.q, s.box, paper_params(w), with_abs=True)
+    assert cond_rel_err(out["f"], F, FA) <= 1e-10
+    assert cond_rel_err(out["torque"], T, TA) <= 1e-10
+    np.testing.assert_allclose(g.particle_energies(), e, rtol=0, atol=1e-12 * np.abs(e).max())
