@@ -114,6 +114,7 @@ def test_null_handle_calls(md):
         assert getattr(lib, name)(None) == -1
     assert lib.md_forces(None, 0) == -1
     assert lib.md_step(None, 1, 0) == -1
+    assert lib.md_thermostat(None, 1.0, 0.5, 1, 0) == -1
     assert lib.md_status_str(-4).decode().startswith("Verlet list overflow")
     assert lib.md_last_error(None).decode() == ""
 

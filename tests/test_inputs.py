@@ -39,3 +39,41 @@ def test_lattice_partial_fill():
     assert len(np.unique(np.round(x / a - 0.5).astype(int), axis=0)) == 131072
     # perfect cubes use the exact side
     assert np.isclose(lattice(4096, 16.0)[:, 0].max(), 15.5)
+
+
+def test_chain_columns_geometry():
+    """The two-patch workload's sites: columns along z spaced box / floor(box /
+    1.04) >= 1.04, on a square (x, y) grid, all inside the box, no two sites
+    closer than the column spacing."""
+    import math
+    from paper_1401_4350_amd.inputs import chain_columns
+    for n, box in ((2000, 15.874), (1001, 12.6), (250, 7.94)):
+        x = chain_columns(n, box)
+        assert x.shape == (n, 3)
+        assert (x >= 0).all() and (x < box).all()
+        nz = int(box // 1.04)
+        b = box / nz
+        assert b >= 1.04
+        # along a column, consecutive sites are b apart
+        col = x[:nz]
+        assert np.allclose(np.diff(col[:, 2]), b)
+        assert np.allclose(col[:, :2], col[0, :2])
+        # the columns' (x, y) spacing is no smaller than b for these densities
+        xy = np.unique(np.round(x[:, :2], 9), axis=0)
+        d = np.abs(xy[:, None, :] - xy[None, :, :]).max(axis=2)
+        d[np.diag_indices_from(d)] = math.inf
+        assert d.min() >= b - 1e-9
+
+
+def test_patchy_paper_orientations():
+    """About 70 % of the two-patch particles start with the body z axis within
+    a small tilt of the lab z axis (the chain direction), the rest uniform."""
+    from paper_1401_4350_amd.inputs import WORKLOADS, make_state
+    w = WORKLOADS["patchy_paper"].with_(n=20000)
+    s = make_state(w, 3)
+    q = s.q
+    # body z axis in the lab frame: third column of R(q)
+    zz = 1 - 2 * (q[:, 1] ** 2 + q[:, 2] ** 2)
+    assert np.allclose(np.linalg.norm(q, axis=1), 1.0)
+    frac = np.mean(zz > np.cos(0.6))
+    assert 0.68 < frac < 0.76
