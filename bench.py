@@ -46,6 +46,21 @@ def vertex_step_bytes(n: int, pairs: int) -> int:
     return 8 * pairs + 148 * n
 
 
+def patchy_vertex_bytes(n: int, pairs: int) -> int:
+    """Algorithmic bytes of one patchy vertex force launch with the closing
+    half kick (FP64): every full-list entry read once (4 B, 2|E| entries), per
+    particle the list length (4 B), its position (24 B) and orientation
+    (32 B), the force and torque written (48 B), the velocity and angular
+    momentum read and written (96 B).  Neighbour records are gathers that the
+    method assumes are cache hits."""
+    return 8 * pairs + 204 * n
+
+
+def step_bytes(w, pairs: int) -> int:
+    """Algorithmic bytes of the vertex force launch of workload w."""
+    return vertex_step_bytes(w.n, pairs) if w.pot == "lj" else patchy_vertex_bytes(w.n, pairs)
+
+
 def edge_pass_bytes(n: int, pairs: int) -> int:
     """Algorithmic bytes of one LJ edge force pass + kick: every half-list
     entry (partner slot 4 B, region index 2 B), per particle the row start
@@ -348,7 +363,7 @@ def main():
     head = runs["vertex"]
     pairs = head["pairs"]
     value = pairs / (head["ms_per_step"] * 1e-3)
-    nb = vertex_step_bytes(w.n, pairs)
+    nb = step_bytes(w, pairs)
     t_kernel = head["force_ms_per_step"] * 1e-3
     achieved = nb / t_kernel / 1e9
 
@@ -367,7 +382,7 @@ def main():
              "edge": summary(runs["edge"], edge_pass_bytes(w.n, runs["edge"]["pairs"]))}
     for k, r in variants.items():
         if k.startswith("vertex"):
-            nbv = vertex_step_bytes(w.n, r["pairs"])
+            nbv = step_bytes(w, r["pairs"])
         elif k == "edge_det":
             nbv = edge_det_bytes(w.n, r["pairs"])
         else:
@@ -380,7 +395,8 @@ def main():
     modes["edge_over_vertex_speedup"] = runs["vertex"]["ms_per_step"] / runs["edge"]["ms_per_step"]
 
     out = {
-        "metric": "pair-force evals/s (LJ MD step, vertex decomposition)",
+        "metric": "pair-force evals/s (%s MD step, vertex decomposition)" % (
+            "LJ" if w.pot == "lj" else "patchy"),
         "value": value,
         "unit": "pair evals/s",
         "n_gpus": 1,
@@ -398,14 +414,16 @@ def main():
                    "max_neighbors": w.list_capacity(), "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_vertex_lj<FP64, closing kick + next kick and drift>",
+                     "kernel": ("k_vertex_lj<FP64, closing kick + next kick and drift>"
+                                if w.pot == "lj" else "k_vertex_patchy<FP64, closing kick>"),
                      "bytes_per_launch": nb, "avg_launch_us": t_kernel * 1e6,
                      # the same kernel against the FP64 vector rate: 2|E| list
-                     # entries of LJ_ENTRY_FLOPS each per launch
-                     "valu": {"achieved": 2 * pairs * LJ_ENTRY_FLOPS / t_kernel / 1e12,
-                              "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                              "frac": 2 * pairs * LJ_ENTRY_FLOPS / t_kernel / 1e12
-                              / FP64_VECTOR_PEAK_TFLOPS}},
+                     # entries of LJ_ENTRY_FLOPS each per launch (LJ only: a
+                     # patchy pair's operation count depends on its geometry)
+                     "valu": ({"achieved": 2 * pairs * LJ_ENTRY_FLOPS / t_kernel / 1e12,
+                               "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": 2 * pairs * LJ_ENTRY_FLOPS / t_kernel / 1e12
+                               / FP64_VECTOR_PEAK_TFLOPS} if w.pot == "lj" else None)},
         "modes": modes,
     }
     # HBM traffic of the same kernel from the committed FETCH_SIZE / WRITE_SIZE
