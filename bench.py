@@ -247,6 +247,45 @@ def locality_bench(torch, steps=100, warmup=20):
     return rows
 
 
+def nvt_bench(torch, target=0.3, steps=6000, every=100, prob=0.1, report=500):
+    """The two-patch workload (131 072 particles, rho = 0.5, prepared at
+    k_B T = 0.15) run in NVT at k_B T = `target`: blocks of `every` vertex
+    steps, each followed by md_thermostat with probability `prob`.  Reports
+    the kinetic temperature 2 E_kin / (6 N) (three translational and three
+    rotational degrees of freedom per particle) every `report` steps, the
+    potential energy per particle, and the MD steps per second with the
+    thermostat calls included."""
+    from paper_1401_4350_amd import md
+    from paper_1401_4350_amd.inputs import WORKLOADS, make_state
+    w = WORKLOADS["patchy_paper"]
+    st = make_state(w, 1)
+    g = md.System(md.make_params(w, "fp64"))
+    g.set_state(st.x, st.v, st.q, st.angmom)
+    g.build()
+    g.forces("vertex")
+    rows = []
+    ke, pe, _ = g.energy()
+    rows.append({"step": 0, "kT": 2 * ke / (6 * w.n), "e_pot": pe / w.n})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, timed = 0, 0.0
+    while done < steps:
+        t1 = time.perf_counter()
+        g.step(every, "vertex")
+        g.thermostat(target, prob, 7, done // every)
+        torch.cuda.synchronize()
+        timed += time.perf_counter() - t1
+        done += every
+        if done % report == 0:
+            ke, pe, _ = g.energy()
+            rows.append({"step": done, "kT": 2 * ke / (6 * w.n), "e_pot": pe / w.n})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    g.close()
+    return {"workload": w.name, "n": w.n, "target_kT": target, "thermostat_every": every,
+            "prob": prob, "md_steps_per_s": steps / timed, "samples": rows,
+            "wall_s": time.perf_counter() - t0}
+
+
 def drift_bench(torch, steps=10000, every=500):
     """Total-energy drift of the 1M-particle LJ workload (dt = 0.005) over
     `steps` velocity-Verlet steps for each precision variant: slope of a
@@ -306,6 +345,8 @@ def main():
                     help="potentials of the crossover sweep (comma-separated)")
     ap.add_argument("--locality", action="store_true",
                     help="cell orders (row-major staged / gathered, Morton, Hilbert) instead of the bench line")
+    ap.add_argument("--nvt", action="store_true",
+                    help="print the NVT run of the two-patch model with the thermostat instead")
     ap.add_argument("--drift", action="store_true",
                     help="print the energy-drift study of the precision variants instead")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -329,6 +370,9 @@ def main():
         return
     if args.drift:
         print(json.dumps({"drift": drift_bench(torch)}), flush=True)
+        return
+    if args.nvt:
+        print(json.dumps({"nvt": nvt_bench(torch)}), flush=True)
         return
     if args.locality:
         print(json.dumps({"locality": locality_bench(torch)}), flush=True)
