@@ -132,3 +132,21 @@ def test_invalid_arguments(md):
         with pytest.raises(md.MDError) as ei:
             g.thermostat(T, p, 1, 0)
         assert ei.value.status == -1
+
+
+def test_nvt_reaches_target_temperature(md):
+    """The two-patch fluid prepared at k_B T = 0.15 and thermostatted at 0.3
+    (every 100 steps, p = 0.3): after 3 000 steps the kinetic temperature,
+    over three translational and three rotational degrees of freedom per
+    particle, is within 10 % of the target."""
+    w = WORKLOADS["patchy_paper"].with_(n=20000)
+    s = accepted_state(w, 6)
+    say("[thermostat nvt] patchy_paper n=20000")
+    g = gpu_system(md, w, s)
+    ke, _, _ = g.energy()
+    assert abs(2 * ke / (6 * w.n) - w.temp) < 0.02
+    for blk in range(30):
+        g.step(100, "vertex")
+        g.thermostat(0.3, 0.3, 11, blk)
+    ke, _, _ = g.energy()
+    assert abs(2 * ke / (6 * w.n) - 0.3) < 0.03
