@@ -21,9 +21,10 @@ SOURCES = [os.path.join(_HERE, "oracle.c")]
 
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` with gcc (-O2, no FMA contraction)."""
+    """Compile ``liboracle.so`` with gcc (-O2, no FMA contraction, OpenMP
+    per-particle loops)."""
     if force or not os.path.exists(LIB_PATH):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99",
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99",
                "-D_DEFAULT_SOURCE", "-o", LIB_PATH + ".tmp"] + SOURCES + ["-lm"]
         subprocess.check_call(cmd, cwd=_HERE)
         os.replace(LIB_PATH + ".tmp", LIB_PATH)
@@ -58,6 +59,13 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         L.or_min_image.restype = ctypes.c_double
         L.or_min_image.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.or_set_threads.restype = None
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_max_threads.restype = ctypes.c_int
+        L.or_max_threads.argtypes = []
+        L.or_patchy_pair_scales.restype = None
+        L.or_patchy_pair_scales.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double,
+                                            ctypes.POINTER(PatchyParams), ctypes.c_int, _D, _D]
         for name in ("or_pairs_brute", "or_pairs_cells"):
             f = getattr(L, name)
             f.restype = ctypes.c_int64
@@ -236,6 +244,31 @@ def patchy_forces(x, q, L, p: Patchy, use_cells=True, with_abs=False):
     lib().or_patchy_forces(n, _d(x), _d(q), L, ctypes.byref(pc), int(use_cells),
                            _d(F), _d(T), _d(e), _d(w), _d(FA), _d(TA))
     return (F, T, e, w, FA, TA) if with_abs else (F, T, e, w)
+
+
+def patchy_pair_scales(x, q, L, p: Patchy, use_cells=True):
+    """(Fpair (N,3), Tpair (N,3)): per component sum_j |F_i(ij)| and
+    sum_j |tau_i(ij)| over the pairs of i -- the magnitudes of the net pair
+    force and torque, where patchy_forces' Fabs / Tabs sum the magnitudes of
+    the individual terms of each pair."""
+    x = _f64(x, (-1, 3))
+    q = _f64(q, (-1, 4))
+    n = x.shape[0]
+    FP, TP = np.zeros((n, 3)), np.zeros((n, 3))
+    pc = p.c()
+    lib().or_patchy_pair_scales(n, _d(x), _d(q), L, ctypes.byref(pc), int(use_cells),
+                                _d(FP), _d(TP))
+    return FP, TP
+
+
+def set_threads(threads: int) -> None:
+    """Threads of the oracle's OpenMP per-particle force loops (results are
+    bitwise independent of the count)."""
+    lib().or_set_threads(int(threads))
+
+
+def max_threads() -> int:
+    return int(lib().or_max_threads())
 
 
 def run(x, v, L, *, pot, nsteps, dt, skin, mass=1.0, inertia=1.0, lj: LJ | None = None,

@@ -8,11 +8,15 @@
  * or_patchy_pair).  Every sum is a straight loop; nothing is blocked, fused or
  * reordered beyond what the definitions state.
  *
- * Build with -O2 -ffp-contract=off so that no multiply-add is fused.
+ * Build with -O2 -ffp-contract=off so that no multiply-add is fused.  The
+ * per-particle loops of the force routines run under OpenMP: every particle's
+ * sums are formed by one thread in the same fixed order of j whatever the
+ * thread count, so the results are bitwise independent of it.
  */
 #include "oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -21,6 +25,10 @@
 /* ------------------------------------------------------------------------- */
 
 double or_min_image(double d, double L) { return d - L * rint(d / L); }
+
+void or_set_threads(int t) { omp_set_num_threads(t > 0 ? t : 1); }
+
+int or_max_threads(void) { return omp_get_max_threads(); }
 
 /* Minimum-image vector from particle i to particle j and its squared length. */
 static double sep(const double* x, int i, int j, double L, double d[3]) {
@@ -231,6 +239,7 @@ void or_lj_forces(int n, const double* x, double L, double eps, double sigma, do
     double rc2 = rc * rc;
     cells_t cl;
     int have = use_cells ? cells_build(&cl, n, x, L, rc) : 0;
+#pragma omp parallel for schedule(dynamic, 64)
     for (int i = 0; i < n; i++) {
         double f3[3] = {0, 0, 0}, a3[3] = {0, 0, 0}, ei = 0, wi = 0, ea = 0;
         if (have) {
@@ -520,6 +529,7 @@ void or_patchy_forces(int n, const double* x, const double* q, double L,
                       double* e, double* w, double* Fabs, double* Tabs) {
     cells_t cl;
     int have = use_cells ? cells_build(&cl, n, x, L, p->rcut) : 0;
+#pragma omp parallel for schedule(dynamic, 64)
     for (int i = 0; i < n; i++) {
         double f3[3] = {0, 0, 0}, t3[3] = {0, 0, 0}, ei = 0, wi = 0;
         double fa[3] = {0, 0, 0}, ta[3] = {0, 0, 0};
@@ -539,6 +549,43 @@ void or_patchy_forces(int n, const double* x, const double* q, double L,
         }
         if (e) e[i] = ei;
         if (w) w[i] = wi;
+    }
+    if (have) cells_free(&cl);
+}
+
+void or_patchy_pair_scales(int n, const double* x, const double* q, double L,
+                           const or_patchy_params* p, int use_cells, double* Fpair,
+                           double* Tpair) {
+    cells_t cl;
+    int have = use_cells ? cells_build(&cl, n, x, L, p->rcut) : 0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < n; i++) {
+        double fa[3] = {0, 0, 0}, ta[3] = {0, 0, 0};
+        double Fj[3], ti[3], tj[3];
+        if (have) {
+            FOR_CANDIDATES(cl, x, L, i, j, {
+                if (j != i) {
+                    or_patchy_pair(&x[3 * i], &x[3 * j], &q[4 * i], &q[4 * j], L, p, Fj, ti, tj);
+                    for (int c = 0; c < 3; c++) {
+                        fa[c] += fabs(Fj[c]); /* |F_i(ij)| = |F_j(ij)| */
+                        ta[c] += fabs(ti[c]);
+                    }
+                }
+            });
+        } else {
+            for (int j = 0; j < n; j++) {
+                if (j == i) continue;
+                or_patchy_pair(&x[3 * i], &x[3 * j], &q[4 * i], &q[4 * j], L, p, Fj, ti, tj);
+                for (int c = 0; c < 3; c++) {
+                    fa[c] += fabs(Fj[c]);
+                    ta[c] += fabs(ti[c]);
+                }
+            }
+        }
+        for (int c = 0; c < 3; c++) {
+            Fpair[3 * i + c] = fa[c];
+            Tpair[3 * i + c] = ta[c];
+        }
     }
     if (have) cells_free(&cl);
 }

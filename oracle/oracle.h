@@ -25,7 +25,7 @@
  * (Hamilton quaternion w,x,y,z), etc.  No function allocates memory that it
  * returns; all outputs go to caller-owned buffers.
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared oracle.c -o liboracle.so -lm
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared oracle.c -o liboracle.so -lm
  */
 #ifndef MD_ORACLE_H
 #define MD_ORACLE_H
@@ -37,6 +37,11 @@ extern "C" {
 
 /* Minimum-image displacement of one component: d - L*rint(d/L). */
 double or_min_image(double d, double L);
+
+/* Threads of the OpenMP per-particle loops of the force routines (results do
+ * not depend on it), and the current maximum. */
+void or_set_threads(int threads);
+int or_max_threads(void);
 
 /* Neighbour set (Verlet list contents, Methods section).  Writes the unordered
  * pairs (i<j) with r_ij < rv into pairs[2*k], pairs[2*k+1] for k < cap and
@@ -111,6 +116,15 @@ double or_patchy_pair(const double* xi, const double* xj, const double* qi,
 void or_patchy_forces(int n, const double* x, const double* q, double L,
                       const or_patchy_params* p, int use_cells, double* F,
                       double* T, double* e, double* w, double* Fabs, double* Tabs);
+
+/* Per-pair scales of the force tolerance: Fpair (3N) gets
+ * sum_j |F_i(ij),c| and Tpair (3N) sum_j |tau_i(ij),c|, the magnitudes of the
+ * net pair force and of the pair's torque on i, summed over the pairs of i.
+ * A pair whose terms cancel contributes less here than to Fabs / Tabs of
+ * or_patchy_forces, which sum the magnitudes of the individual terms. */
+void or_patchy_pair_scales(int n, const double* x, const double* q, double L,
+                           const or_patchy_params* p, int use_cells, double* Fpair,
+                           double* Tpair);
 
 /* ---- Integration ------------------------------------------------------------ */
 typedef struct {
