@@ -17,12 +17,14 @@
  *                   zero (Methods section, "edge-based" approach; Fig. 1 right).
  *   MD_MODE_NEWTON  the vertex approach with Newton's third law (Discussion
  *                   section, Fig. S2): the threads of particle i walk its half
- *                   list (j > i), evaluate each pair once, keep -F for i and add
- *                   +F to j atomically -- into one of m replicated force arrays
- *                   that a closing pass sums (md_params.newton_m = m >= 1, as
- *                   in the paper), or, with newton_m = 0, into a per-workgroup
- *                   LDS accumulator over the tile's neighbour region that is
- *                   added to the forces once per workgroup.  LJ only.
+ *                   list (j > i), evaluate each pair once, keep -F (and tau_i)
+ *                   for i and add +F (and tau_j) to j atomically -- into one
+ *                   of m replicated force (and torque) arrays that a closing
+ *                   pass sums (md_params.newton_m = m >= 1, as in the paper),
+ *                   or, with newton_m = 0, for LJ into a per-workgroup LDS
+ *                   accumulator over the tile's neighbour region that is
+ *                   added to the forces once per workgroup, for patchy
+ *                   particles straight into the force and torque arrays.
  *   MD_MODE_EDGE_DET the edge approach made deterministic as the Methods
  *                   section describes as its alternative to atomics: one
  *                   thread per half-list entry stores the pair's result per
@@ -120,7 +122,8 @@ typedef struct {
     double patch_rcut;     /* patch-patch cut-off; <= 0 means none                    */
     double inertia;        /* isotropic moment of inertia > 0                        */
     /* MD_MODE_NEWTON only */
-    int32_t newton_m;      /* replicated force arrays, 1 .. 64; 0: LDS accumulation  */
+    int32_t newton_m;      /* replicated force (and torque) arrays, 1 .. 64; 0: none  */
+                           /* (LJ: LDS accumulation, patchy: atomics into F and tau)  */
     int32_t edge_store;    /* 1: workspace for MD_MODE_EDGE_DET (32 B (LJ) or 96 B    */
                            /* (patchy) per half-list entry, 4 B per full-list slot);  */
                            /* 0: none.  Half-list capacity below 2^31 entries          */
@@ -156,6 +159,11 @@ typedef struct {
     int32_t n_cells;        /* cells per box side                                  */
     int32_t tiles_total;    /* tiles of the vertex pass                            */
     int32_t tiles_staged;   /* tiles whose neighbour region was staged in LDS      */
+    int64_t nonzero_pairs;  /* half-list entries whose pair result (force, or for
+                               patchy either torque) is non-zero at the current
+                               positions, in the configured precision: the pairs
+                               whose atomics the edge pass does not skip (Methods
+                               section); 0 without built lists                   */
 } md_stats_t;
 
 /* Sizes of the two device buffers a system needs (pure host, no HIP call).
@@ -220,7 +228,8 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode);
  * (A1, A2), (A3, B0), (B1, B2) give v_x, v_y, v_z, then L_x, L_y, L_z.  The
  * same (seed, counter) gives the same draws; use a new counter per call.
  * Positions and forces are unchanged.  Errors: temperature < 0 or not finite,
- * prob outside [0, 1], no state.  Async. */
+ * prob outside [0, 1] (MD_ERR_INVALID_ARG); no state, or md_build_cells not
+ * yet followed by md_build_neighbors (MD_ERR_STATE).  Async. */
 md_status md_thermostat(md_system* s, double temperature, double prob, uint64_t seed,
                         uint64_t counter);
 
@@ -244,19 +253,24 @@ md_status md_get_state(md_system* s, double* x, double* v, double* f, double* q,
  * Syncs. */
 md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pairs);
 
-/* Counters; syncs. */
+/* Counters; syncs.  With built lists it also counts nonzero_pairs: fills the
+ * half list if needed and evaluates every half-list pair once (a pass of the
+ * cost of an edge force pass, without its atomics). */
 md_status md_stats(md_system* s, md_stats_t* out);
 
 /* Per-phase GPU time of md_step, from HIP events recorded on the system's
  * stream around each phase of every step while profiling is enabled:
  * integrate (half kick + drift + rebuild test), rebuild (cell sort and list
- * build kernels, which return at once when no rebuild is due) and force (the
- * force pass, including the fused closing half kick; for the edge mode also
- * the separate kick kernel).  Times are summed over the steps taken since
- * profiling was enabled. */
+ * build kernels, which return at once when no rebuild is due), force (the
+ * force kernels: for the LJ vertex pass the one kernel that also does the
+ * closing half kick and the next step's half kick and drift; for the edge
+ * and Newton passes the on-demand half-list fill, which returns at once
+ * between builds, and the force kernel) and kick (the separate closing half
+ * kick kernel of the passes that do not fuse it; zero otherwise).  Times are
+ * summed over the steps taken since profiling was enabled. */
 typedef struct {
     int64_t steps;
-    double integrate_ms, rebuild_ms, force_ms;
+    double integrate_ms, rebuild_ms, force_ms, kick_ms;
 } md_profile_t;
 
 /* Enables (on != 0) or disables event timing of md_step and clears the sums.
@@ -288,8 +302,9 @@ void md_destroy(md_system* s);
  * each launched with its own LDS, so that systems with large regions do not
  * lower the occupancy of the others.  A launch runs steps_per_launch steps
  * (fewer when no system needs that many) as one hipGraph; grids are the
- * blocks in use rounded up to a power of two, and a graph is captured the
- * first time a combination of grids occurs (a few dozen are kept).
+ * blocks in use rounded up to a power of two.  A graph is captured once per
+ * step count; when admissions and retirements change the grids, its kernel
+ * nodes are re-gridded in place, without a new capture.
  * ------------------------------------------------------------------------- */
 typedef struct md_batch md_batch; /* opaque handle */
 
@@ -348,6 +363,7 @@ typedef struct {
     uint64_t bytes;          /* sum of their footprints                              */
     int64_t launches;        /* md_batch_step launches so far                        */
     int64_t captures;        /* graphs captured so far                               */
+    int64_t regrids;         /* captured graphs re-gridded in place (no recapture)   */
 } md_batch_info_t;
 
 md_status md_batch_info(const md_batch* b, md_batch_info_t* out);

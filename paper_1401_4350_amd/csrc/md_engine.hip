@@ -215,7 +215,8 @@ Layout layout(const md_params& p) {
     L.hstart = take(cur, 4 * (n + 1));
     L.hj = take(cur, 4 * (uint64_t)L.max_half);
     L.hr = take(cur, p.pot == MD_POT_LJ ? 2 * (uint64_t)L.max_half : 0);
-    L.rep = take(cur, p.pot == MD_POT_LJ ? 32 * n * (uint64_t)p.newton_m : 0);
+    // Newton mode replicas: m force arrays (and for patchy m torque arrays)
+    L.rep = take(cur, (p.pot == MD_POT_LJ ? 32 : 64) * n * (uint64_t)p.newton_m);
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
     L.bsum = take(cur, 4 * (uint64_t)std::max(L.nblk, L.ntiles));  // per-tile half totals
     L.tmax = take(cur, 4 * (uint64_t)L.ntiles);
@@ -337,18 +338,14 @@ md_status md_query_sizes(const md_params* p, md_sizes* out) {
     return MD_OK;
 }
 
-md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, void* d_workspace,
-                    uint64_t workspace_bytes, void* hip_stream, md_system** out) {
-    if (!out) return MD_ERR_INVALID_ARG;
-    *out = nullptr;
-    md_status st = validate(p);
-    if (st != MD_OK) return st;
-    if (!d_state || !d_workspace) return MD_ERR_INVALID_ARG;
-    Layout L = layout(*p);
-    if (state_bytes < L.state_bytes || workspace_bytes < L.ws_bytes) return MD_ERR_BUFFER_TOO_SMALL;
-    if ((uintptr_t)d_state % kAlign || (uintptr_t)d_workspace % kAlign)
-        return MD_ERR_BUFFER_TOO_SMALL;
+}  // extern "C"
 
+namespace {
+
+// md_create with the workspace given (validated by the caller).
+md_status create_system(const md_params* p, const Layout& L, void* d_state, void* d_workspace,
+                        void* hip_stream, md_system** out) {
+    md_status st = MD_OK;
     md_system* s = new md_system();
     s->p = *p;
     s->lay = L;
@@ -408,7 +405,7 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     y.hj = (int*)(W + L.hj);
     y.hr = (uint16_t*)(W + L.hr);
     y.rep = (double4*)(W + L.rep);
-    y.nrep = p->pot == MD_POT_LJ ? p->newton_m : 0;
+    y.nrep = p->newton_m;
     y.chunk_row = (int*)(W + L.chunk_row);
     y.bsum = (int*)(W + L.bsum);
     y.tmax = (int*)(W + L.tmax);
@@ -440,7 +437,8 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     st = s->hip(hipMemsetAsync(y.ccount, 0, 4 * (size_t)L.ncell, s->stream), "clear cell counts");
     if (st == MD_OK) st = s->hip(hipMemsetAsync(d_state, 0, L.state_bytes, s->stream), "clear state");
     if (st == MD_OK && y.nrep > 0)  // replicas start at zero; the combining pass re-zeroes them
-        st = s->hip(hipMemsetAsync(y.rep, 0, 32 * (size_t)p->n * y.nrep, s->stream), "clear replicas");
+        st = s->hip(hipMemsetAsync(y.rep, 0, (patchy ? 64 : 32) * (size_t)p->n * y.nrep, s->stream),
+                    "clear replicas");
     std::vector<int> ranks;  // cell order table, copied before the stream is drained
     if (st == MD_OK && y.cell_rank) {
         ranks.resize(L.ncell);
@@ -458,6 +456,25 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     *out = s;
     return MD_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, void* d_workspace,
+                    uint64_t workspace_bytes, void* hip_stream, md_system** out) {
+    if (!out) return MD_ERR_INVALID_ARG;
+    *out = nullptr;
+    md_status st = validate(p);
+    if (st != MD_OK) return st;
+    if (!d_state || !d_workspace) return MD_ERR_INVALID_ARG;
+    Layout L = layout(*p);
+    if (state_bytes < L.state_bytes || workspace_bytes < L.ws_bytes) return MD_ERR_BUFFER_TOO_SMALL;
+    if ((uintptr_t)d_state % kAlign || (uintptr_t)d_workspace % kAlign)
+        return MD_ERR_BUFFER_TOO_SMALL;
+    return create_system(p, L, d_state, d_workspace, hip_stream, out);
+}
+
 
 md_status md_set_state(md_system* s, const double* x, const double* v, const double* q,
                        const double* angmom) {
@@ -549,8 +566,6 @@ static md_status check_mode(md_system* s, int32_t mode) {
     if (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE && mode != MD_MODE_NEWTON &&
         mode != MD_MODE_EDGE_DET)
         return s->fail(MD_ERR_INVALID_ARG, "mode");
-    if (mode == MD_MODE_NEWTON && s->p.pot != MD_POT_LJ)
-        return s->fail(MD_ERR_INVALID_ARG, "the Newton mode is implemented for LJ only");
     if (mode == MD_MODE_EDGE_DET && !s->p.edge_store)
         return s->fail(MD_ERR_INVALID_ARG, "the deterministic edge mode needs edge_store = 1 at md_create");
     return MD_OK;
@@ -589,13 +604,14 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     // passes that add with atomics into the force array need it cleared first
     bool edge = mode == MD_MODE_EDGE || (mode == MD_MODE_NEWTON && s->sys.nrep == 0);
     bool prof = s->profiling;
+    constexpr size_t kEv = 5;  // events per profiled step
     if (prof) {
-        md_status r = s->hip(s->ensure_events(4 * (size_t)nsteps), "profile events");
+        md_status r = s->hip(s->ensure_events(kEv * (size_t)nsteps), "profile events");
         if (r != MD_OK) return r;
     }
     hipStream_t st = s->stream;
     for (int k = 0; k < nsteps; k++) {
-        hipEvent_t* ev = prof ? &s->events[4 * (size_t)k] : nullptr;
+        hipEvent_t* ev = prof ? &s->events[kEv * (size_t)k] : nullptr;
         hipError_t e = prof ? hipEventRecord(ev[0], st) : hipSuccess;
         if (e == hipSuccess && (!fuse || k == 0)) e = md::launch_kick_drift(y, edge, st);
         if (e == hipSuccess && prof) e = hipEventRecord(ev[1], st);
@@ -604,10 +620,14 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
         if (fuse && k + 1 < nsteps) {
             if (e == hipSuccess) e = md::launch_vertex_kick_drift(y, s->p.prec, st);
             std::swap(y.pos, y.pos_alt);
+            if (e == hipSuccess && prof) e = hipEventRecord(ev[3], st);
         } else if (e == hipSuccess) {
-            e = md::launch_forces(y, mode, s->p.prec, true, st, s->edge_grid);
+            // the closing kick of the passes without a fused one comes after
+            // event 3, so the force phase times the force kernels alone
+            e = md::launch_forces(y, mode, s->p.prec, true, st, s->edge_grid,
+                                  prof ? ev[3] : nullptr);
         }
-        if (e == hipSuccess && prof) e = hipEventRecord(ev[3], st);
+        if (e == hipSuccess && prof) e = hipEventRecord(ev[4], st);
         if (e != hipSuccess) {
             s->sys = y;
             return s->hip(e, "step launch");
@@ -618,15 +638,17 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     md_status r = s->sync_check();
     if (r != MD_OK || !prof) return r;
     for (int k = 0; k < nsteps; k++) {
-        hipEvent_t* ev = &s->events[4 * (size_t)k];
-        float a = 0, b = 0, c = 0;
+        hipEvent_t* ev = &s->events[kEv * (size_t)k];
+        float a = 0, b = 0, c = 0, d = 0;
         hipError_t e = hipEventElapsedTime(&a, ev[0], ev[1]);
         if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[1], ev[2]);
         if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[2], ev[3]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&d, ev[3], ev[4]);
         if (e != hipSuccess) return s->hip(e, "profile elapsed");
         s->prof.integrate_ms += a;
         s->prof.rebuild_ms += b;
         s->prof.force_ms += c;
+        s->prof.kick_ms += d;
     }
     s->prof.steps += nsteps;
     return MD_OK;
@@ -639,6 +661,9 @@ md_status md_thermostat(md_system* s, double temperature, double prob, uint64_t 
     if (!std::isfinite(temperature) || !(temperature >= 0) || !(prob >= 0) || !(prob <= 1))
         return s->fail(MD_ERR_INVALID_ARG, "thermostat needs temperature >= 0 and 0 <= prob <= 1");
     if (!s->state_set) return s->fail(MD_ERR_STATE, "md_set_state first");
+    // between md_build_cells and md_build_neighbors the momenta sit in the
+    // reorder buffers, which the list build copies back over the state
+    if (s->cells_pending) return s->fail(MD_ERR_STATE, "md_build_neighbors first");
     const double sv = std::sqrt(temperature / s->p.mass);
     const double sl = s->p.pot == MD_POT_PATCHY ? std::sqrt(s->p.inertia * temperature) : 0.0;
     return s->hip(md::launch_thermostat(s->sys, sv, sl, prob, seed, counter, s->stream),
@@ -782,7 +807,13 @@ md_status md_get_pairs(md_system* s, int32_t* pairs, int64_t cap, int64_t* n_pai
 md_status md_stats(md_system* s, md_stats_t* out) {
     if (!s || !out) return MD_ERR_INVALID_ARG;
     if (s->batch) return s->admitted();
-    md_status r = s->hip(hipStreamSynchronize(s->stream), "stats sync");
+    md_status r = MD_OK;
+    if (s->lists_valid) {  // the edge pass's non-zero pairs at the current positions
+        r = s->hip(md::launch_half_fill(s->sys, s->stream), "half fill");
+        if (r == MD_OK) r = s->hip(md::launch_count_nonzero(s->sys, s->p.prec, s->stream), "count");
+        if (r != MD_OK) return r;
+    }
+    r = s->hip(hipStreamSynchronize(s->stream), "stats sync");
     md::Ctrl c;
     if (r == MD_OK) r = s->hip(hipMemcpy(&c, s->sys.ctrl, sizeof c, hipMemcpyDeviceToHost), "ctrl");
     if (r != MD_OK) return r;
@@ -793,6 +824,7 @@ md_status md_stats(md_system* s, md_stats_t* out) {
     out->n_cells = s->lay.nc;
     out->tiles_total = s->lay.ntiles;
     out->tiles_staged = c.staged;
+    out->nonzero_pairs = s->lists_valid ? c.nonzero : 0;
     return MD_OK;
 }
 
@@ -884,18 +916,23 @@ struct md_batch {
     int active = 0;
     long long particles = 0;
     uint64_t bytes = 0;
-    // Captured launches, keyed by steps and the grid of every class.  Grids
-    // are the blocks in use rounded up to a power of two, so admissions and
-    // retirements reuse a captured graph until a class crosses a power of two.
+    // Captured launches, one per step count.  Grids are the blocks in use
+    // rounded up to a power of two (at least one block, so every kernel of
+    // the step is a node); when admissions change them, the kernel nodes of
+    // the instantiated graph are re-gridded in place (each node's class from
+    // its kernel), so a graph is captured once per step count.
     struct Graph {
         int steps;
         int grid[md::kNumClasses];
+        hipGraph_t graph;
         hipGraphExec_t exec;
+        std::vector<std::pair<hipGraphNode_t, int>> nodes;  // kernel node, its class
+        bool regriddable;  // every node is a known batch kernel
         long long used_at;
     };
     std::vector<Graph> graphs;
-    static constexpr size_t kMaxGraphs = 24;
-    long long launches = 0, captures = 0;
+    static constexpr size_t kMaxGraphs = 8;
+    long long launches = 0, captures = 0, regrids = 0;
     std::string err;
 
     md_status fail(md_status st, const std::string& msg) {
@@ -907,18 +944,23 @@ struct md_batch {
         err = std::string(where) + ": " + hipGetErrorString(e);
         return MD_ERR_HIP;
     }
+    void drop_graph(Graph& g) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
     void drop_graphs() {
-        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+        for (auto& g : graphs) drop_graph(g);
         graphs.clear();
     }
     // Grid of every class for the current admissions: the blocks in use,
-    // rounded up to a power of two for captured graphs; 0 for a bucket class
-    // no admitted system uses (not launched).
+    // rounded up to a power of two for captured graphs; a bucket class no
+    // admitted system uses gets 0 blocks (not launched) for direct launches
+    // and 1 idle block in a graph.
     void grids(bool bucket, int* out) const {
         for (int c = 0; c < md::kNumClasses; c++) {
             bool bucketed = c >= md::kClsVertex0;
             if (bucketed && used[c] == 0) {
-                out[c] = 0;
+                out[c] = bucket ? 1 : 0;
                 continue;
             }
             int u = std::max(used[c], 1);
@@ -971,20 +1013,68 @@ struct md_batch {
         return r;
     }
 
+    // Kernel nodes of a captured step with their classes; false if a node is
+    // not one of the batch kernels (the graph is then re-captured instead of
+    // re-gridded).
+    bool collect_nodes(Graph& g) {
+        size_t n = 0;
+        if (hipGraphGetNodes(g.graph, nullptr, &n) != hipSuccess) return false;
+        std::vector<hipGraphNode_t> all(n);
+        if (n && hipGraphGetNodes(g.graph, all.data(), &n) != hipSuccess) return false;
+        for (hipGraphNode_t node : all) {
+            hipGraphNodeType type;
+            if (hipGraphNodeGetType(node, &type) != hipSuccess || type != hipGraphNodeTypeKernel)
+                return false;
+            hipKernelNodeParams kp{};
+            if (hipGraphKernelNodeGetParams(node, &kp) != hipSuccess) return false;
+            int cls = md::batch_kernel_class(kp.func);
+            if (cls == -2) return false;
+            if (cls >= 0) g.nodes.emplace_back(node, cls);
+        }
+        return true;
+    }
+
+    // Sets the grid of every node whose class changed; false on failure.
+    bool regrid(Graph& g, const int* grid) {
+        if (!g.regriddable) return false;
+        for (auto& nc : g.nodes) {
+            if (g.grid[nc.second] == grid[nc.second]) continue;
+            hipKernelNodeParams kp{};
+            if (hipGraphKernelNodeGetParams(nc.first, &kp) != hipSuccess) return false;
+            kp.gridDim = dim3((unsigned)grid[nc.second]);
+            if (hipGraphExecKernelNodeSetParams(g.exec, nc.first, &kp) != hipSuccess) return false;
+            if (hipGraphKernelNodeSetParams(nc.first, &kp) != hipSuccess) return false;
+        }
+        std::copy(grid, grid + md::kNumClasses, g.grid);
+        regrids++;
+        return true;
+    }
+
     md_status graph_for(int steps, const int* grid, hipGraphExec_t* out) {
-        for (auto& g : graphs)
-            if (g.steps == steps && std::equal(grid, grid + md::kNumClasses, g.grid)) {
-                g.used_at = launches;
-                *out = g.exec;
-                return MD_OK;
+        for (size_t k = 0; k < graphs.size(); k++) {
+            Graph& g = graphs[k];
+            if (g.steps != steps) continue;
+            if (!std::equal(grid, grid + md::kNumClasses, g.grid)) {
+                // the previous launch of this graph may still run
+                md_status r = hip(hipStreamSynchronize(stream), "regrid sync");
+                if (r != MD_OK) return r;
+                if (!regrid(g, grid)) {  // not re-griddable: capture anew
+                    drop_graph(g);
+                    graphs.erase(graphs.begin() + k);
+                    break;
+                }
             }
+            g.used_at = launches;
+            *out = g.exec;
+            return MD_OK;
+        }
         if (graphs.size() >= kMaxGraphs) {  // drop the least recently launched
             auto old = std::min_element(graphs.begin(), graphs.end(), [](const Graph& a, const Graph& b) {
                 return a.used_at < b.used_at;
             });
             md_status r = hip(hipStreamSynchronize(stream), "graph eviction sync");
             if (r != MD_OK) return r;
-            (void)hipGraphExecDestroy(old->exec);
+            drop_graph(*old);
             graphs.erase(old);
         }
         hipGraph_t graph = nullptr;
@@ -995,14 +1085,18 @@ struct md_batch {
         r = hip(e != hipSuccess ? e : e2, "capture batch step");
         hipGraphExec_t exec = nullptr;
         if (r == MD_OK) r = hip(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "instantiate");
-        if (graph) (void)hipGraphDestroy(graph);
-        if (r != MD_OK) return r;
+        if (r != MD_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return r;
+        }
         Graph g;
         g.steps = steps;
         std::copy(grid, grid + md::kNumClasses, g.grid);
+        g.graph = graph;
         g.exec = exec;
         g.used_at = launches;
-        graphs.push_back(g);
+        g.regriddable = collect_nodes(g);
+        graphs.push_back(std::move(g));
         captures++;
         *out = exec;
         return MD_OK;
@@ -1173,6 +1267,7 @@ md_status md_batch_info(const md_batch* b, md_batch_info_t* out) {
     out->bytes = b->bytes;
     out->launches = b->launches;
     out->captures = b->captures;
+    out->regrids = b->regrids;
     return MD_OK;
 }
 

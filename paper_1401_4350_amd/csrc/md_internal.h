@@ -37,7 +37,8 @@ struct Ctrl {
     long long rebuilds; // number of builds
     int half_stale;     // the half list predates the last build (filled on demand)
     int eidx_stale;     // the edge index of the full-list entries predates the half list
-    long long pad[2];
+    long long nonzero;  // half-list entries with a non-zero pair result (md_stats)
+    long long pad1;
 };
 
 // Completion counters of the kernels whose last workgroup runs an epilogue
@@ -226,6 +227,11 @@ __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
 // is not launched).
 hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int steps,
                               hipStream_t st);
+// Block class of a kernel of the batched step (by its host function): the
+// class whose grid it is launched with, -1 for a kernel of fixed grid, -2 for
+// a function that is not one of them.  Lets a captured step be re-gridded in
+// place when admissions change the blocks in use.
+int batch_kernel_class(const void* func);
 
 // Host-side launchers (md_kernels.hip).  All enqueue on `st`.
 hipError_t launch_set_rebuild(const Sys& s, hipStream_t st);
@@ -234,14 +240,20 @@ hipError_t launch_rebuild(const Sys& s, hipStream_t st, bool cells, bool lists);
 // Fills the half list if the last build made it stale (returns at once
 // otherwise); the edge and Newton passes and the pair download need it.
 hipError_t launch_half_fill(const Sys& s, hipStream_t st);
+// With kick, `mid` (if not null) is recorded between the force kernels and
+// a separate closing kick kernel (after the force kernel when the kick is
+// fused into it).
 hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_t st,
-                         int edge_grid);
+                         int edge_grid, hipEvent_t mid = nullptr);
 hipError_t launch_kick_drift(const Sys& s, bool zero_forces, hipStream_t st);
 // LJ vertex forces with the closing half kick and the next step's half kick,
 // drift (into pos_alt) and rebuild test.
 hipError_t launch_vertex_kick_drift(const Sys& s, int prec, hipStream_t st);
 hipError_t launch_kick(const Sys& s, hipStream_t st);
 hipError_t launch_energy(const Sys& s, int prec, hipStream_t st);
+// Counts into ctrl->nonzero (cleared first) the half-list entries whose pair
+// result is non-zero at the current positions; needs a filled half list.
+hipError_t launch_count_nonzero(const Sys& s, int prec, hipStream_t st);
 hipError_t launch_clear_rebuild(const Sys& s, hipStream_t st);
 
 // Momentum refresh of the NVT thermostat (sv = sqrt(T / m), sl = sqrt(I T)).

@@ -96,8 +96,6 @@ __device__ __forceinline__ double wrap_box(double y, double L) {
     return y;
 }
 
-// 1/a from the hardware reciprocal refined by two Newton steps (to within an
-// ulp of the correctly rounded quotient for normal a).
 // 1 / a from the hardware reciprocal (relative error 4.6e-8 on gfx950) and
 // one Newton step: relative error below 2.2e-15 over the r^2 range of the
 // pair maths (measured against a long-double reference on 4M arguments).
@@ -338,6 +336,7 @@ __global__ void k_clear_ctrl(Ctrl* c, int* sync) {
     c->rebuilds = 0;
     c->half_stale = 0;
     c->eidx_stale = 0;
+    c->nonzero = 0;
 }
 
 // True in the one workgroup, of the nb that call this with the same counter,
@@ -1793,6 +1792,59 @@ __global__ __launch_bounds__(kBlock) void k_edge(Sys s) {
     b_edge<POT, PREC, STORE>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
+// Half-list entries whose pair result (the force, or for patchy particles
+// either torque) is non-zero at the current positions, evaluated in the
+// system's precision: the pairs whose atomics the edge pass does not skip
+// (Methods section: only non-zero interactions are written).  One thread per
+// entry, its row by binary search over the row starts; one 64-bit atomic per
+// wavefront into ctrl->nonzero.  Counting only: no force is written.
+template <int POT, int PREC>
+__global__ __launch_bounds__(kBlock) void k_count_nonzero(Sys s) {
+    using R = typename std::conditional<PREC == 0, double, float>::type;
+    const long long npairs = s.ctrl->npairs;
+    unsigned long long cnt = 0;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < npairs;
+         e += (long long)gridDim.x * kBlock) {
+        int lo = 0, hi = s.n - 1;  // last row whose start is <= e
+        while (lo < hi) {
+            const int mid = lo + (hi - lo + 1) / 2;
+            if ((long long)s.hstart[mid] <= e) lo = mid;
+            else hi = mid - 1;
+        }
+        const int ent = s.hj[e];
+        const int j = min(entry_slot(ent), s.n - 1);
+        const double4 xi = s.pos[lo], xj = s.pos[j];
+        const double dx = xj.x - xi.x + image(ent, 0, s.box);
+        const double dy = xj.y - xi.y + image(ent, 1, s.box);
+        const double dz = xj.z - xi.z + image(ent, 2, s.box);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        bool nz = false;
+        if (r2 < s.rc2) {
+            if (POT == 0) {
+                const R fr = PREC == 0 ? (R)lj_fr<double>(r2, s.l64, nullptr)
+                                       : (R)lj_fr<float>((float)r2, s.l32, nullptr);
+                nz = ((R)dx * fr != R(0)) | ((R)dy * fr != R(0)) | ((R)dz * fr != R(0));
+            } else {
+                V3<double> ui[4], uj[4];
+                patch_dirs<double>(s.quat[lo], ui, s.p64.model);
+                patch_dirs<double>(s.quat[j], uj, s.p64.model);
+                const V3<double> d = {dx, dy, dz};
+                V3<double> fj, ti, tj;
+                double v;
+                patchy_pair<R>(d, r2, ui, uj, s, fj, ti, tj, v);
+                nz = (fj.x != 0.0) | (fj.y != 0.0) | (fj.z != 0.0) | (ti.x != 0.0) |
+                     (ti.y != 0.0) | (ti.z != 0.0) | (tj.x != 0.0) | (tj.y != 0.0) | (tj.z != 0.0);
+            }
+        }
+        cnt += nz ? 1u : 0u;
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & (kWave - 1)) == 0 && cnt)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&s.ctrl->nonzero), cnt);
+}
+
+__global__ void k_zero_nonzero(Ctrl* c) { c->nonzero = 0; }
+
 // Deterministic edge mode, second pass: four lanes per particle sum the
 // stored results of its edges (-F as the edge's first member, +F as its
 // second; tau_i or tau_j), lane q the entries q, q + 4, ... of its list in
@@ -2090,8 +2142,106 @@ __global__ __launch_bounds__(kBlock) void k_newton_lj(Sys s) {
     b_newton_lj<PREC, REP>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
-// Closing pass of the replicated Newton mode: F += sum of the replicas, which
-// are cleared for the next pass; optionally the closing half kick.
+// Newton's-third-law vertex pass for patchy particles (the paper's Discussion
+// section: where it pays, it does so for the models with few, expensive
+// interactions).  TPP lanes per particle (patchy_vertex_tpp) walk its half
+// list; each pair is evaluated once, -F_ij and tau_i stay in registers, +F_ij
+// and tau_j go to the partner atomically, each skipped when exactly zero.
+// REP: into one of nrep replicated force and torque arrays (chosen per
+// wavefront), i's own sums stored straight into F and tau (their only
+// writer), then k_newton_combine; !REP: device-scope atomics into F and tau,
+// which must be zero on entry (the patchy passes stage no region in LDS).
+template <int PREC, bool REP, int TPP>
+__device__ __forceinline__ void b_newton_patchy(const Sys& s, int bid, int nb) {
+    using R = typename std::conditional<PREC == 0, double, float>::type;
+    const int i = bid * (kBlock / TPP) + (int)threadIdx.x / TPP;
+    const int q = (int)threadIdx.x % TPP;
+    const bool act = i < s.n;
+    const int ii = act ? i : s.n - 1;
+    const int e0 = act ? s.hstart[ii] : 0;
+    const int e1 = act ? s.hstart[ii + 1] : 0;
+    const double4 xi = s.pos[ii];
+    V3<double> ui[4];
+    patch_dirs<double>(s.quat[ii], ui, s.p64.model);
+    double* F = reinterpret_cast<double*>(s.frc);
+    double* T = reinterpret_cast<double*>(s.trq);
+    if (REP) {
+        const long long wave = ((long long)bid * kBlock + threadIdx.x) / kWave;
+        const size_t r = (size_t)(wave % s.nrep);
+        F = reinterpret_cast<double*>(s.rep + r * s.n);
+        T = reinterpret_cast<double*>(s.rep + (s.nrep + r) * (size_t)s.n);
+    }
+    Acc3<PREC> f, tq;
+    for (int e = e0 + q; e < e1; e += TPP) {
+        const int ent = s.hj[e];
+        const int j = min(entry_slot(ent), s.n - 1);
+        const double4 xj = s.pos[j];
+        const double dx = xj.x - xi.x + image(ent, 0, s.box);
+        const double dy = xj.y - xi.y + image(ent, 1, s.box);
+        const double dz = xj.z - xi.z + image(ent, 2, s.box);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (!(r2 < s.rc2)) continue;
+        V3<double> uj[4];
+        patch_dirs<double>(s.quat[j], uj, s.p64.model);
+        const V3<double> d = {dx, dy, dz};
+        V3<double> fj, ti, tj;
+        double v;
+        patchy_pair<R>(d, r2, ui, uj, s, fj, ti, tj, v);
+        f.add(-fj.x, -fj.y, -fj.z);
+        tq.add(ti.x, ti.y, ti.z);
+        if ((fj.x != 0.0) | (fj.y != 0.0) | (fj.z != 0.0)) {
+            double* g = F + 4 * (size_t)j;
+            unsafeAtomicAdd(g + 0, fj.x);
+            unsafeAtomicAdd(g + 1, fj.y);
+            unsafeAtomicAdd(g + 2, fj.z);
+        }
+        if ((tj.x != 0.0) | (tj.y != 0.0) | (tj.z != 0.0)) {
+            double* g = T + 4 * (size_t)j;
+            unsafeAtomicAdd(g + 0, tj.x);
+            unsafeAtomicAdd(g + 1, tj.y);
+            unsafeAtomicAdd(g + 2, tj.z);
+        }
+    }
+    double fx = f.gx(), fy = f.gy(), fz = f.gz();
+    double tx = tq.gx(), ty = tq.gy(), tz = tq.gz();
+#pragma unroll
+    for (int off = 1; off < TPP; off <<= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+        tx += __shfl_xor(tx, off);
+        ty += __shfl_xor(ty, off);
+        tz += __shfl_xor(tz, off);
+    }
+    if (!act || q != 0) return;
+    if (REP) {
+        s.frc[i] = make_double4(fx, fy, fz, 0.0);
+        s.trq[i] = make_double4(tx, ty, tz, 0.0);
+        return;
+    }
+    double* Fi = reinterpret_cast<double*>(s.frc) + 4 * (size_t)i;
+    double* Ti = reinterpret_cast<double*>(s.trq) + 4 * (size_t)i;
+    if ((fx != 0.0) | (fy != 0.0) | (fz != 0.0)) {
+        unsafeAtomicAdd(Fi + 0, fx);
+        unsafeAtomicAdd(Fi + 1, fy);
+        unsafeAtomicAdd(Fi + 2, fz);
+    }
+    if ((tx != 0.0) | (ty != 0.0) | (tz != 0.0)) {
+        unsafeAtomicAdd(Ti + 0, tx);
+        unsafeAtomicAdd(Ti + 1, ty);
+        unsafeAtomicAdd(Ti + 2, tz);
+    }
+}
+
+template <int PREC, bool REP, int TPP>
+__global__ __launch_bounds__(kBlock) void k_newton_patchy(Sys s) {
+    b_newton_patchy<PREC, REP, TPP>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Closing pass of the replicated Newton mode: F (and tau) += sum of the
+// replicas, which are cleared for the next pass; optionally the closing half
+// kick (and the angular one).  Patchy replicas: nrep force arrays, then nrep
+// torque arrays.
 template <bool KICK>
 __global__ __launch_bounds__(kBlock) void k_newton_combine(Sys s) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -2107,13 +2257,33 @@ __global__ __launch_bounds__(kBlock) void k_newton_combine(Sys s) {
         *p = make_double4(0.0, 0.0, 0.0, 0.0);
     }
     s.frc[i] = f;
-    if (!isfinite(f.x + f.y + f.z)) atomicOr(&s.ctrl->nonfinite, 1);
+    double4 tq = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (s.pot == 1) {
+        tq = s.trq[i];
+        for (int r = 0; r < s.nrep; r++) {
+            double4* p = s.rep + (size_t)(s.nrep + r) * s.n + i;
+            const double4 v = *p;
+            tq.x += v.x;
+            tq.y += v.y;
+            tq.z += v.z;
+            *p = make_double4(0.0, 0.0, 0.0, 0.0);
+        }
+        s.trq[i] = tq;
+    }
+    if (!isfinite(f.x + f.y + f.z + tq.x + tq.y + tq.z)) atomicOr(&s.ctrl->nonfinite, 1);
     if (KICK) {
         double4 v = s.vel[i];
         v.x += s.hdt * f.x * s.inv_mass;
         v.y += s.hdt * f.y * s.inv_mass;
         v.z += s.hdt * f.z * s.inv_mass;
         s.vel[i] = v;
+        if (s.pot == 1) {
+            double4 L = s.angm[i];
+            L.x += s.hdt * tq.x;
+            L.y += s.hdt * tq.y;
+            L.z += s.hdt * tq.z;
+            s.angm[i] = L;
+        }
     }
 }
 
@@ -2368,6 +2538,18 @@ static void edge_dispatch(const Sys& s, int grid, hipStream_t st) {
 template <int PREC>
 static void newton_dispatch(const Sys& s, hipStream_t st) {
     dim3 g((unsigned)s.ntiles), b(kBlock);
+    if (s.pot == 1) {
+        const bool lanes = patchy_vertex_tpp(s) > 1;
+        const dim3 gp((unsigned)(lanes ? s.ntiles : s.nblk));
+        if (s.nrep > 0) {
+            if (lanes) hipLaunchKernelGGL((k_newton_patchy<PREC, true, kTileTpp>), gp, b, 0, st, s);
+            else hipLaunchKernelGGL((k_newton_patchy<PREC, true, 1>), gp, b, 0, st, s);
+        } else {
+            if (lanes) hipLaunchKernelGGL((k_newton_patchy<PREC, false, kTileTpp>), gp, b, 0, st, s);
+            else hipLaunchKernelGGL((k_newton_patchy<PREC, false, 1>), gp, b, 0, st, s);
+        }
+        return;
+    }
     if (s.nrep > 0) {
         hipLaunchKernelGGL((k_newton_lj<PREC, true>), g, b, 0, st, s);
     } else {
@@ -2376,22 +2558,27 @@ static void newton_dispatch(const Sys& s, hipStream_t st) {
     }
 }
 
-hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_t st, int edge_grid) {
+hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_t st, int edge_grid,
+                         hipEvent_t mid) {
+    // closing kick of the passes without a fused one, after the `mid` event
+    auto closing_kick = [&](bool newton_combine) {
+        if (mid) (void)hipEventRecord(mid, st);  // an error surfaces below
+        if (newton_combine) hipLaunchKernelGGL(k_newton_combine<true>, grid_n(s.n), dim3(kBlock), 0, st, s);
+        else if (s.pot == 0) hipLaunchKernelGGL(k_kick<0>, grid_n(s.n), dim3(kBlock), 0, st, s);
+        else hipLaunchKernelGGL(k_kick<1>, grid_n(s.n), dim3(kBlock), 0, st, s);
+    };
     if (mode == 0) {
         if (prec == 0) vertex_dispatch<0>(s, kick, false, st);
         else if (prec == 1) vertex_dispatch<1>(s, kick, false, st);
         else vertex_dispatch<2>(s, kick, false, st);
-    } else if (mode == 2) {  // Newton (LJ); with atomics into F it must start at zero
+        if (kick && mid) (void)hipEventRecord(mid, st);
+    } else if (mode == 2) {  // Newton; with atomics into F (and tau) it must start at zero
         (void)launch_half_fill(s, st);  // launch errors surface in hipGetLastError below
         if (s.nrep == 0 && !kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) newton_dispatch<0>(s, st);
         else newton_dispatch<1>(s, st);  // FP32 pair maths, FP64 sums
-        if (s.nrep > 0) {
-            if (kick) hipLaunchKernelGGL(k_newton_combine<true>, grid_n(s.n), dim3(kBlock), 0, st, s);
-            else hipLaunchKernelGGL(k_newton_combine<false>, grid_n(s.n), dim3(kBlock), 0, st, s);
-        } else if (kick) {
-            hipLaunchKernelGGL(k_kick<0>, grid_n(s.n), dim3(kBlock), 0, st, s);
-        }
+        if (kick) closing_kick(s.nrep > 0);
+        else if (s.nrep > 0) hipLaunchKernelGGL(k_newton_combine<false>, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (!kick) hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
     } else if (mode == 3) {  // deterministic edge: per-edge results, then a gather
         if (!s.estore) return hipErrorInvalidValue;
@@ -2406,23 +2593,15 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
             else hipLaunchKernelGGL((k_edge<1, 1, true>), g, b, 0, st, s);
             hipLaunchKernelGGL(k_edge_gather<1>, dim3((unsigned)s.ntiles), b, 0, st, s);
         }
-        if (kick) {
-            if (s.pot == 0) hipLaunchKernelGGL(k_kick<0>, grid_n(s.n), dim3(kBlock), 0, st, s);
-            else hipLaunchKernelGGL(k_kick<1>, grid_n(s.n), dim3(kBlock), 0, st, s);
-        } else {
-            hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
-        }
+        if (kick) closing_kick(false);
+        else hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
     } else {
         (void)launch_half_fill(s, st);  // launch errors surface in hipGetLastError below
         if (!kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) edge_dispatch<0>(s, edge_grid, st);
         else edge_dispatch<1>(s, edge_grid, st);  // FP32 pair maths, FP64 atomics
-        if (kick) {
-            if (s.pot == 0) hipLaunchKernelGGL(k_kick<0>, grid_n(s.n), dim3(kBlock), 0, st, s);
-            else hipLaunchKernelGGL(k_kick<1>, grid_n(s.n), dim3(kBlock), 0, st, s);
-        } else {
-            hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
-        }
+        if (kick) closing_kick(false);
+        else hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
     }
     return hipGetLastError();
 }
@@ -2525,6 +2704,21 @@ hipError_t launch_thermostat(const Sys& s, double sv, double sl, double prob, ui
                              uint64_t counter, hipStream_t st) {
     hipLaunchKernelGGL(k_thermostat, grid_n(s.n), dim3(kBlock), 0, st, s, sv, sl, prob, seed,
                        counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonzero(const Sys& s, int prec, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_nonzero, dim3(1), dim3(1), 0, st, s.ctrl);
+    const long long waves = (s.max_half + kWave - 1) / kWave;
+    const dim3 g((unsigned)std::max(1LL, std::min((waves + 3) / 4, 8192LL)));
+    const dim3 b(kBlock);
+    if (s.pot == 0) {
+        if (prec == 0) hipLaunchKernelGGL((k_count_nonzero<0, 0>), g, b, 0, st, s);
+        else hipLaunchKernelGGL((k_count_nonzero<0, 1>), g, b, 0, st, s);
+    } else {
+        if (prec == 0) hipLaunchKernelGGL((k_count_nonzero<1, 0>), g, b, 0, st, s);
+        else hipLaunchKernelGGL((k_count_nonzero<1, 1>), g, b, 0, st, s);
+    }
     return hipGetLastError();
 }
 
@@ -2675,5 +2869,27 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
     hipLaunchKernelGGL(kb_advance, dim3((b.nslots + kBlock - 1) / kBlock), blk, 0, st, b, steps);
     return hipGetLastError();
 }
+
+int batch_kernel_class(const void* func) {
+    const void* particle[] = {reinterpret_cast<const void*>(&kb_kick_drift<false>),
+                              reinterpret_cast<const void*>(&kb_kick_drift<true>),
+                              reinterpret_cast<const void*>(&kb_cell_bin),
+                              reinterpret_cast<const void*>(&kb_cell_scatter),
+                              reinterpret_cast<const void*>(&kb_build),
+                              reinterpret_cast<const void*>(&kb_kick)};
+    for (const void* f : particle)
+        if (f == func) return kClsParticle;
+    if (func == reinterpret_cast<const void*>(&kb_sort_tiles)) return kClsSortTiles;
+    if (func == reinterpret_cast<const void*>(&kb_half_fill)) return kClsTile;
+    if (func == reinterpret_cast<const void*>(&kb_vertex<kClsVertex0>)) return kClsVertex0;
+    if (func == reinterpret_cast<const void*>(&kb_vertex<kClsVertex1>)) return kClsVertex1;
+    if (func == reinterpret_cast<const void*>(&kb_vertex<kClsVertex2>)) return kClsVertex2;
+    if (func == reinterpret_cast<const void*>(&kb_edge<kClsEdge0>)) return kClsEdge0;
+    if (func == reinterpret_cast<const void*>(&kb_edge<kClsEdge1>)) return kClsEdge1;
+    if (func == reinterpret_cast<const void*>(&kb_edge<kClsEdge2>)) return kClsEdge2;
+    if (func == reinterpret_cast<const void*>(&kb_advance)) return -1;
+    return -2;
+}
+
 
 }  // namespace md

@@ -51,12 +51,13 @@ class MDStats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("rebuilds", ctypes.c_int64),
                 ("pairs", ctypes.c_int64), ("max_list_len", ctypes.c_int32),
                 ("n_cells", ctypes.c_int32), ("tiles_total", ctypes.c_int32),
-                ("tiles_staged", ctypes.c_int32)]
+                ("tiles_staged", ctypes.c_int32), ("nonzero_pairs", ctypes.c_int64)]
 
 
 class MDProfile(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("integrate_ms", ctypes.c_double),
-                ("rebuild_ms", ctypes.c_double), ("force_ms", ctypes.c_double)]
+                ("rebuild_ms", ctypes.c_double), ("force_ms", ctypes.c_double),
+                ("kick_ms", ctypes.c_double)]
 
 
 class MDBatchParams(ctypes.Structure):
@@ -68,7 +69,8 @@ class MDBatchParams(ctypes.Structure):
 class MDBatchInfo(ctypes.Structure):
     _fields_ = [("active", ctypes.c_int32), ("lds_cap", ctypes.c_int32),
                 ("particles", ctypes.c_int64), ("bytes", ctypes.c_uint64),
-                ("launches", ctypes.c_int64), ("captures", ctypes.c_int64)]
+                ("launches", ctypes.c_int64), ("captures", ctypes.c_int64),
+                ("regrids", ctypes.c_int64)]
 
 
 _P = ctypes.c_void_p
@@ -184,11 +186,11 @@ class System:
         a = int(sz.alignment)
         # over-allocate by one alignment unit and align the base pointer
         self._state = torch.empty(int(sz.state_bytes) + a, dtype=torch.uint8, device=dev)
-        self._ws = torch.empty(int(sz.workspace_bytes) + a, dtype=torch.uint8, device=dev)
         sp = (self._state.data_ptr() + a - 1) // a * a
-        wp = (self._ws.data_ptr() + a - 1) // a * a
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _sys_p()
+        self._ws = torch.empty(int(sz.workspace_bytes) + a, dtype=torch.uint8, device=dev)
+        wp = (self._ws.data_ptr() + a - 1) // a * a
         st = _lib.md_create(ctypes.byref(params), sp, sz.state_bytes, wp, sz.workspace_bytes,
                             self.stream.cuda_stream, ctypes.byref(h))
         if st != MD_OK:
@@ -285,14 +287,15 @@ class System:
         p = MDProfile()
         self._check(_lib.md_profile_read(self._h, ctypes.byref(p)), "md_profile_read")
         return dict(steps=p.steps, integrate_ms=p.integrate_ms, rebuild_ms=p.rebuild_ms,
-                    force_ms=p.force_ms)
+                    force_ms=p.force_ms, kick_ms=p.kick_ms)
 
     def stats(self) -> dict:
         s = MDStats()
         self._check(_lib.md_stats(self._h, ctypes.byref(s)), "md_stats")
         return dict(steps=s.steps, rebuilds=s.rebuilds, pairs=s.pairs,
                     max_list_len=s.max_list_len, n_cells=s.n_cells,
-                    tiles_total=s.tiles_total, tiles_staged=s.tiles_staged)
+                    tiles_total=s.tiles_total, tiles_staged=s.tiles_staged,
+                    nonzero_pairs=s.nonzero_pairs)
 
 
 def batch_params(max_systems: int, max_particles: int, pool_bytes: int, mode: str = "vertex",
@@ -377,7 +380,7 @@ class Batch:
         i = MDBatchInfo()
         self._check(_lib.md_batch_info(self._h, ctypes.byref(i)), "md_batch_info")
         return dict(active=i.active, lds_cap=i.lds_cap, particles=i.particles, bytes=i.bytes,
-                    launches=i.launches, captures=i.captures)
+                    launches=i.launches, captures=i.captures, regrids=i.regrids)
 
     def close(self):
         if getattr(self, "_h", None):

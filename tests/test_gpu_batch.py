@@ -2,12 +2,16 @@
 gives the same result alone (md_step) and in a mix of systems of different
 size, potential, density and precision -- bitwise in the vertex mode, within
 1e-9 in the edge mode (FP64 atomics add in a different order) -- including
-systems admitted and retired while others run, and the batch's error paths."""
+systems admitted and retired while others run, and the batch's error paths.
+Every FP64 system's batched trajectory is also compared with the oracle's
+velocity-Verlet run: positions, velocities (and quaternions, angular momenta)
+within 1e-9 and the same number of list builds."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_1401_4350_amd.inputs import WORKLOADS
 
 from _helpers import accepted_state
@@ -47,6 +51,37 @@ def fresh(md, k, seed=11):
     g.set_state(s.x, s.v, s.q, s.angmom)
     g.build()
     return g, steps
+
+
+def oracle_run(k, seed=11):
+    """The oracle's run of MIX[k] from the same accepted state as fresh()."""
+    name, over, prec, steps = MIX[k]
+    w = WORKLOADS[name].with_(**over)
+    s = accepted_state(w, seed + k)
+    if w.pot == "lj":
+        return w, oracle.run(s.x, s.v, s.box, pot="lj", nsteps=steps, dt=w.dt, skin=w.skin,
+                             mass=w.mass, lj=oracle.LJ(w.eps, w.sigma, w.rcut))
+    pp = oracle.Patchy(eps=w.eps, sigma=w.sigma, rcut=w.rcut, eps_p=w.eps_p, w=w.patch_w,
+                       delta=w.patch_delta, rpc=w.patch_rcut,
+                       model=1 if w.patch_model == "polar2" else 0)
+    return w, oracle.run(s.x, s.v, s.box, pot="patchy", nsteps=steps, dt=w.dt, skin=w.skin,
+                         mass=w.mass, inertia=w.inertia, patchy=pp, q=s.q, angmom=s.angmom)
+
+
+def check_against_oracle(k, got, gstats):
+    w, ref = oracle_run(k)
+    d = got["x"] - ref["x"]
+    d -= w.box * np.rint(d / w.box)
+    assert np.abs(d).max() < 1e-9, (k, "x")
+    assert np.abs(got["v"] - ref["v"]).max() < 1e-9, (k, "v")
+    if w.pot == "patchy":
+        # q and -q are the same rotation
+        dq = np.minimum(np.abs(got["q"] - ref["q"]).max(axis=1),
+                        np.abs(got["q"] + ref["q"]).max(axis=1))
+        assert dq.max() < 1e-9, (k, "q")
+        assert np.abs(got["angmom"] - ref["angmom"]).max() < 1e-9, (k, "angmom")
+    if ref["disp_margin"] > 1e-12:
+        assert gstats["rebuilds"] == len(ref["rebuild_steps"]), k
 
 
 def alone(md, k, mode):
@@ -101,6 +136,9 @@ def test_batch_vertex_bitwise_alone_and_in_mix(md, use_graph):
             assert np.array_equal(got[key], ref[key]), (k, key)
         assert gstats["steps"] == rstats["steps"] == MIX[k][3]
         assert gstats["rebuilds"] == rstats["rebuilds"]
+        if use_graph and MIX[k][2] == "fp64":
+            say(f"  oracle run of system {k}")
+            check_against_oracle(k, got, gstats)
 
 
 def test_batch_edge_alone_and_in_mix(md):
@@ -115,6 +153,8 @@ def test_batch_edge_alone_and_in_mix(md):
         tol = 1e-9 if MIX[k][2] == "fp64" else 1e-6
         assert np.abs(d).max() < tol, k
         assert np.abs(got["v"] - ref["v"]).max() < tol, k
+        if MIX[k][2] == "fp64":
+            check_against_oracle(k, got, mix[k][1])
 
 
 def test_batch_cancel_and_slot_reuse(md):

@@ -226,3 +226,27 @@ def test_call_order_errors(md):
     assert ei.value.status == -7
     with pytest.raises(md.MDError):
         g.build_neighbors()
+    # between the cell sort and the list build the momenta sit in the reorder
+    # buffers: a thermostat call there would be lost, so it is refused
+    s = accepted_state(w, 9)
+    g.set_state(s.x, s.v)
+    g.build_cells()
+    with pytest.raises(md.MDError) as ei:
+        g.thermostat(1.0, 0.5, 1, 0)
+    assert ei.value.status == -7
+    g.build_neighbors()
+    g.thermostat(1.0, 0.5, 1, 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nonzero_pairs(md, prec):
+    """md_stats' nonzero_pairs: the half-list pairs with a non-zero LJ force,
+    i.e. those with r < r_c (the force vanishes exactly only at isolated
+    distances no seeded pair hits), against the oracle's pair set at r_c."""
+    w = WORKLOADS["lj_small"].with_(n=3000)
+    s = accepted_state(w, 10)
+    say(f"[nonzero pairs] {prec}")
+    g = gpu_system(md, w, s, prec)
+    st = g.stats()
+    assert st["pairs"] == len(oracle.pairs(s.x, s.box, w.rv))
+    assert st["nonzero_pairs"] == len(oracle.pairs(s.x, s.box, w.rcut))

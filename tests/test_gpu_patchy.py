@@ -166,3 +166,24 @@ def test_sparse_half_list(md, mode):
     assert np.count_nonzero(np.abs(T).sum(1)) > 100
     assert cond_rel_err(out["f"], F, FP) <= 1e-10
     assert cond_rel_err(out["torque"], T, TP) <= 1e-10
+
+
+def test_patchy_nonzero_pairs(md):
+    """md_stats' nonzero_pairs for patchy particles: half-list pairs whose
+    force or either torque is non-zero, against the oracle's pair function
+    evaluated on every listed pair."""
+    w = WORKLOADS["patchy"].with_(n=1200)
+    s = accepted_state(w, 21)
+    say("[patchy nonzero pairs]")
+    g = gpu_system(md, w, s)
+    st = g.stats()
+    pairs = oracle.pairs(s.x, s.box, w.rv)
+    assert st["pairs"] == len(pairs)
+    pp = patchy_params(w)
+    nz = 0
+    for i, j in pairs:
+        _, fj, ti, tj = oracle.patchy_pair(s.x[i], s.x[j], s.q[i], s.q[j], s.box, pp)
+        nz += bool(np.any(fj != 0) or np.any(ti != 0) or np.any(tj != 0))
+    assert st["nonzero_pairs"] == nz
+    assert 0 < nz < len(pairs)
+
