@@ -214,7 +214,8 @@ Layout layout(const md_params& p) {
     L.hcount = take(cur, 4 * n);
     L.hstart = take(cur, 4 * (n + 1));
     L.hj = take(cur, 4 * (uint64_t)L.max_half);
-    L.hr = take(cur, p.pot == MD_POT_LJ ? 2 * (uint64_t)L.max_half : 0);
+    // packed words, four spare (the edge pass reads them four at a time)
+    L.hr = take(cur, p.pot == MD_POT_LJ ? 4 * ((uint64_t)L.max_half + 4) : 0);
     // Newton mode replicas: m force arrays (and for patchy m torque arrays)
     L.rep = take(cur, (p.pot == MD_POT_LJ ? 32 : 64) * n * (uint64_t)p.newton_m);
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
@@ -342,15 +343,11 @@ md_status md_query_sizes(const md_params* p, md_sizes* out) {
 
 namespace {
 
-// md_create with the workspace given (validated by the caller).
-md_status create_system(const md_params* p, const Layout& L, void* d_state, void* d_workspace,
-                        void* hip_stream, md_system** out) {
-    md_status st = MD_OK;
-    md_system* s = new md_system();
-    s->p = *p;
-    s->lay = L;
-    s->stream = (hipStream_t)hip_stream;
-    md::Sys& y = s->sys;
+// The kernels' descriptor of a system whose state and workspace start at
+// d_state and d_workspace (carved as `layout` says); *edge_grid gets the
+// block count of the edge pass.
+void fill_sys(const md_params* p, const Layout& L, void* d_state, void* d_workspace, md::Sys& y,
+              int* edge_grid) {
     std::memset(&y, 0, sizeof y);
     char* S = (char*)d_state;
     char* W = (char*)d_workspace;
@@ -403,7 +400,7 @@ md_status create_system(const md_params* p, const Layout& L, void* d_state, void
     y.hcount = (int*)(W + L.hcount);
     y.hstart = (int*)(W + L.hstart);
     y.hj = (int*)(W + L.hj);
-    y.hr = (uint16_t*)(W + L.hr);
+    y.hr = (unsigned*)(W + L.hr);
     y.rep = (double4*)(W + L.rep);
     y.nrep = p->newton_m;
     y.chunk_row = (int*)(W + L.chunk_row);
@@ -429,9 +426,22 @@ md_status create_system(const md_params* p, const Layout& L, void* d_state, void
 
     long long waves = (L.max_half + md::kWave - 1) / md::kWave;
     long long blocks = (waves + 3) / 4;
-    s->edge_grid = (int)std::max(1LL, std::min(blocks, 4096LL));
-    y.eblk = std::min(s->edge_grid, 4 * L.ntiles);  // edge blocks when stepped in a batch
+    *edge_grid = (int)std::max(1LL, std::min(blocks, 4096LL));
+    y.eblk = std::min(*edge_grid, 4 * L.ntiles);  // edge blocks when stepped in a batch
     y.prec = p->prec;
+}
+
+// md_create with the workspace given (validated by the caller).
+md_status create_system(const md_params* p, const Layout& L, void* d_state, void* d_workspace,
+                        void* hip_stream, md_system** out) {
+    md_status st = MD_OK;
+    md_system* s = new md_system();
+    s->p = *p;
+    s->lay = L;
+    s->stream = (hipStream_t)hip_stream;
+    md::Sys& y = s->sys;
+    fill_sys(p, L, d_state, d_workspace, y, &s->edge_grid);
+    bool patchy = p->pot == MD_POT_PATCHY;
 
     // One-time clears at creation (never inside a captured step).
     st = s->hip(hipMemsetAsync(y.ccount, 0, 4 * (size_t)L.ncell, s->stream), "clear cell counts");

@@ -115,7 +115,7 @@ struct Sys {
     int* hcount;
     int* hstart;     // n + 1
     int* hj;         // half-list partner slots, CSR by row
-    uint16_t* hr;    // LJ: LDS region index of each half-list entry of a staged tile
+    unsigned* hr;    // LJ, staged tiles: per half-list entry, row in the tile << 16 | region index
     double4* rep;    // Newton mode: nrep replicated force arrays of n records
     int nrep;
     int* chunk_row;  // first row of every 64-pair chunk of the half list
@@ -179,7 +179,7 @@ constexpr int kLdsBuckets = 3;
 
 // Largest region capacity (slots) of each LDS bucket: with 24-byte records,
 // bucket 0 leaves room for four workgroups per CU, bucket 1 for three.
-__host__ __device__ inline int bucket_cap(int b) {
+__host__ __device__ constexpr int bucket_cap(int b) {
     return b == 0 ? 1664 : (b == 1 ? 2240 : kLdsCapMax);
 }
 

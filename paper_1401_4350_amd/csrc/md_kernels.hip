@@ -1169,7 +1169,9 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
         if (s.estore && keep) eidx_row(s, i)[list_off(q + m * TPP)] = kk < end ? (int)kk : -1;
         if (keep && kk < end) {
             s.hj[kk] = ent;
-            if (nseg >= 0) s.hr[kk] = (uint16_t)reg;  // the edge pass accumulates by region
+            // the edge pass accumulates by region index and finds the row in
+            // the high half
+            if (nseg >= 0) s.hr[kk] = (unsigned)reg | (unsigned)(i - tile * kTile) << 16;
         }
         k += __builtin_popcount(grp);
     }
@@ -1931,22 +1933,40 @@ __device__ __forceinline__ void region_acc_flush(const Sys& s, const double* acc
     }
 }
 
-// LJ edge pass, one workgroup per tile of kTile rows: the tile's half-list
-// entries (contiguous, rows in slot order) are spread over the workgroup's
-// lanes, one entry per lane.  Each lane evaluates its pair once from global
-// positions.  The j side is added with LDS atomics into an accumulator laid
-// out like the tile's staged region (the half list records each entry's
-// region index), the i side is combined per row with a segmented shuffle
-// reduction and added into a per-row LDS accumulator; at the end every
+// LJ edge pass, one workgroup per tile of kTile rows (the rows' half-list
+// entries are contiguous, in row order).
+//
+// Tiles with a staged region (b_edge_lj_staged): the region's positions are
+// copied into LDS as the vertex pass copies them, and each lane takes four
+// consecutive half-list entries with one 16-byte load of their packed words
+// (row in the tile << 16 | region index of the partner): no global gather
+// and no search for the row.  Each pair is evaluated once; the partner's
+// share goes into an LDS accumulator over the region with LDS atomics, the
+// row's share is summed in registers over the lane's run of entries of one
+// row and added to a per-row LDS accumulator once per run.  At the end every
 // non-zero accumulator is added to global memory with one atomic per
-// component, the region in runs of consecutive slots.  Tiles without a staged
-// region add their j side straight to global memory.  Forces must be zero on
-// entry.
+// component (the region in runs of consecutive slots).  Zero results are
+// skipped throughout.
+//
+// Other tiles (b_edge_lj_gather): one entry per lane, positions gathered from
+// global memory, the row found by binary search over the tile's row starts,
+// the partner's share added with global atomics, the row's share combined by
+// a segmented shuffle reduction.  Forces must be zero on entry.
+
+// Dynamic LDS of the LJ edge pass: with staged positions the region copy and
+// its accumulator, else the accumulator alone (regions too large for both
+// run every tile through the gather path).
+constexpr int kEdgeStageCapMax = 3072;
+__host__ __device__ constexpr bool edge_stages_positions(int cap) { return cap <= kEdgeStageCapMax; }
+__host__ __device__ __forceinline__ size_t edge_lds_bytes(int cap) {
+    return (edge_stages_positions(cap) ? lds_region_bytes(cap) : 0) + lds_acc_bytes(cap);
+}
+
 template <int PREC>
-__device__ __forceinline__ void b_edge_lj_tile(const Sys& s, int tile, int nb) {
+__device__ __forceinline__ void b_edge_lj_gather(const Sys& s, int tile, double* tsh) {
     extern __shared__ double acc[];
-    __shared__ int hs[kTile + 1];
-    __shared__ double fi[3 * kTile];
+    double* fi = tsh;                          // per-row sums
+    int* hs = reinterpret_cast<int*>(tsh + 3 * kTile);  // the rows' half-list starts
     const int lane = threadIdx.x & (kWave - 1);
     const int cap = s.lds_cap;
     const int plane = lds_plane(cap);
@@ -1996,7 +2016,7 @@ __device__ __forceinline__ void b_edge_lj_tile(const Sys& s, int tile, int nb) {
         const bool nz = (fx != 0.0) | (fy != 0.0) | (fz != 0.0);
         if (nz) {
             if (staged) {
-                const int r = s.hr[es];
+                const int r = s.hr[es] & 0xffff;
                 unsafeAtomicAdd(&acc[r], fx);
                 unsafeAtomicAdd(&acc[plane + r], fy);
                 unsafeAtomicAdd(&acc[2 * plane + r], fz);
@@ -2034,9 +2054,139 @@ __device__ __forceinline__ void b_edge_lj_tile(const Sys& s, int tile, int nb) {
     }
 }
 
+
 template <int PREC>
+__device__ __forceinline__ void lj_edge_pair(const Sys& s, double dx, double dy, double dz,
+                                             double& fx, double& fy, double& fz) {
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const bool in = r2 < s.rc2;
+    if (PREC == 0) {
+        const double inv = rcp_nr(r2);
+        const double s2 = s.l64.sig2 * inv;
+        const double s6 = s2 * s2 * s2;
+        const double fr = s.l64.eps24 * inv * s6 * (2.0 * s6 - 1.0) * (in ? 1.0 : 0.0);
+        fx = fr * dx;
+        fy = fr * dy;
+        fz = fr * dz;
+    } else {
+        const float r2f = (float)r2;
+        const float inv = rcp_nr(r2f);
+        const float s2 = s.l32.sig2 * inv;
+        const float s6 = s2 * s2 * s2;
+        const float fr = s.l32.eps24 * inv * s6 * (2.0f * s6 - 1.0f) * (in ? 1.0f : 0.0f);
+        fx = fr * (float)dx;
+        fy = fr * (float)dy;
+        fz = fr * (float)dz;
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ void b_edge_lj_staged(const Sys& s, int tile, double* tsh) {
+    extern __shared__ double lds3[];  // region positions, then the accumulator
+    double* fi = tsh;                 // per-row sums
+    double* xr = tsh + 3 * kTile;     // the tile's own positions
+    const int cap = s.lds_cap;
+    const int plane = lds_plane(cap);
+    double* acc = lds3 + 3 * (cap + 1);
+    const int t0 = tile * kTile;
+    const int nrow = min(kTile, s.n - t0);
+    const int e0 = s.hstart[t0], e1 = s.hstart[t0 + nrow];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int nchk = s.tile_nchunk[tile];
+    RegionBatch rb;
+    region_issue(s, s.pos, tile, nchk, wv, rb);
+    // first block of packed entries: lane k takes entries a + 4k .. a + 4k + 3
+    // (a = e0 rounded down to a multiple of four, so the load is aligned; the
+    // allocation has four spare entries after the last)
+    const int a0 = e0 & ~3;
+    const int4* hw = reinterpret_cast<const int4*>(s.hr);
+    int4 w = a0 + 4 * (int)threadIdx.x < e1 ? hw[(a0 >> 2) + threadIdx.x] : make_int4(0, 0, 0, 0);
+    for (int k = threadIdx.x; k < 3 * plane; k += kBlock) acc[k] = 0.0;
+    if (threadIdx.x < 3 * kTile) fi[threadIdx.x] = 0.0;
+    if (threadIdx.x < nrow) {
+        const double4 p = s.pos[t0 + threadIdx.x];
+        xr[3 * threadIdx.x] = p.x;
+        xr[3 * threadIdx.x + 1] = p.y;
+        xr[3 * threadIdx.x + 2] = p.z;
+    }
+    region_store(s, lds3, rb);
+    region_finish(s, s.pos, lds3, cap, tile, nchk, wv, rb);  // ends with the barrier
+    for (int base = a0; base < e1; base += 4 * kBlock) {
+        const int eb = base + 4 * (int)threadIdx.x;
+        const int nxt = eb + 4 * kBlock;
+        const int4 wn = nxt < e1 ? hw[(nxt >> 2)] : make_int4(0, 0, 0, 0);
+        const int wd[4] = {w.x, w.y, w.z, w.w};
+        int row[4], reg[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const bool ok = eb + u >= e0 && eb + u < e1;
+            row[u] = ok ? (wd[u] >> 16) : -1;
+            reg[u] = ok ? (wd[u] & 0xffff) : cap;  // the padding slot: no force
+        }
+        double gx[4], gy[4], gz[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int ri = max(row[u], 0);
+            const double* pj = lds3 + 3 * reg[u];
+            const double* pi = xr + 3 * ri;
+            lj_edge_pair<PREC>(s, pj[0] - pi[0], pj[1] - pi[1], pj[2] - pi[2], gx[u], gy[u], gz[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if ((gx[u] != 0.0) | (gy[u] != 0.0) | (gz[u] != 0.0)) {
+                unsafeAtomicAdd(&acc[reg[u]], gx[u]);
+                unsafeAtomicAdd(&acc[plane + reg[u]], gy[u]);
+                unsafeAtomicAdd(&acc[2 * plane + reg[u]], gz[u]);
+            }
+        }
+        // the row's share: the sum over each run of equal rows (rows ascend)
+        double sx = 0, sy = 0, sz = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            sx -= gx[u];
+            sy -= gy[u];
+            sz -= gz[u];
+            const bool last = u == 3 || row[u + 1] != row[u];
+            if (last) {
+                if (row[u] >= 0 && ((sx != 0.0) | (sy != 0.0) | (sz != 0.0))) {
+                    unsafeAtomicAdd(&fi[3 * row[u]], sx);
+                    unsafeAtomicAdd(&fi[3 * row[u] + 1], sy);
+                    unsafeAtomicAdd(&fi[3 * row[u] + 2], sz);
+                }
+                sx = sy = sz = 0;
+            }
+        }
+        w = wn;
+    }
+    __syncthreads();
+    double* F = reinterpret_cast<double*>(s.frc);
+    region_acc_flush(s, acc, plane, tile, F);
+    if (threadIdx.x < nrow) {
+        const double vx = fi[3 * threadIdx.x], vy = fi[3 * threadIdx.x + 1],
+                     vz = fi[3 * threadIdx.x + 2];
+        if ((vx != 0.0) | (vy != 0.0) | (vz != 0.0)) {
+            double* g = F + 4 * (size_t)(t0 + threadIdx.x);
+            unsafeAtomicAdd(g + 0, vx);
+            unsafeAtomicAdd(g + 1, vy);
+            unsafeAtomicAdd(g + 2, vz);
+        }
+    }
+}
+
+// STAGE: the launch's dynamic LDS holds the region copy as well
+// (edge_lds_bytes), so staged tiles take b_edge_lj_staged.
+template <int PREC, bool STAGE>
+__device__ __forceinline__ void b_edge_lj_tile(const Sys& s, int tile, int nb) {
+    // per-row sums, then the rows' positions (staged) or row starts (gather)
+    __shared__ double tsh[6 * kTile];
+    static_assert(sizeof(int) * (kTile + 1) <= sizeof(double) * 3 * kTile, "row starts fit");
+    if (STAGE && s.tile_nseg[tile] >= 0) b_edge_lj_staged<PREC>(s, tile, tsh);
+    else b_edge_lj_gather<PREC>(s, tile, tsh);
+}
+
+template <int PREC, bool STAGE>
 __global__ __launch_bounds__(kBlock) void k_edge_lj_tile(Sys s) {
-    b_edge_lj_tile<PREC>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+    b_edge_lj_tile<PREC, STAGE>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -2103,7 +2253,7 @@ __device__ __forceinline__ void b_newton_lj(const Sys& s, int tile, int nb) {
             fz -= gz;
             if ((gx != 0.0) | (gy != 0.0) | (gz != 0.0)) {
                 if (staged) {
-                    const int r = s.hr[e];
+                    const int r = s.hr[e] & 0xffff;
                     unsafeAtomicAdd(&acc[r], gx);
                     unsafeAtomicAdd(&acc[plane + r], gy);
                     unsafeAtomicAdd(&acc[2 * plane + r], gz);
@@ -2528,8 +2678,11 @@ template <int PREC>
 static void edge_dispatch(const Sys& s, int grid, hipStream_t st) {
     dim3 g(grid), b(kBlock);
     if (s.pot == 0) {
-        size_t sh = lds_acc_bytes(s.lds_cap);
-        hipLaunchKernelGGL((k_edge_lj_tile<PREC>), dim3((unsigned)s.ntiles), b, sh, st, s);
+        const size_t sh = edge_lds_bytes(s.lds_cap);
+        if (edge_stages_positions(s.lds_cap))
+            hipLaunchKernelGGL((k_edge_lj_tile<PREC, true>), dim3((unsigned)s.ntiles), b, sh, st, s);
+        else
+            hipLaunchKernelGGL((k_edge_lj_tile<PREC, false>), dim3((unsigned)s.ntiles), b, sh, st, s);
     } else {
         hipLaunchKernelGGL((k_edge<1, PREC>), g, b, 0, st, s);
     }
@@ -2808,8 +2961,9 @@ template <int C>
 __global__ __launch_bounds__(kBlock) void kb_edge(BatchDev b, int step) {
     batch_block<C>(b, step, [](const Sys& s, int lb) {
         if (s.pot == 0) {
-            if (s.prec == 0) b_edge_lj_tile<0>(s, lb, s.ntiles);
-            else b_edge_lj_tile<1>(s, lb, s.ntiles);
+            constexpr bool stage = edge_stages_positions(bucket_cap(C - kClsEdge0));
+            if (s.prec == 0) b_edge_lj_tile<0, stage>(s, lb, s.ntiles);
+            else b_edge_lj_tile<1, stage>(s, lb, s.ntiles);
         } else {
             if (s.prec == 0) b_edge<1, 0>(s, lb, s.eblk);
             else b_edge<1, 1>(s, lb, s.eblk);
@@ -2861,7 +3015,7 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
                 constexpr int B = decltype(bk)::value;
                 if (grid[kClsEdge0 + B] > 0)
                     hipLaunchKernelGGL(kb_edge<kClsEdge0 + B>, g(kClsEdge0 + B), blk,
-                                       lds_acc_bytes(bucket_cap(B)), st, b, k);
+                                       edge_lds_bytes(bucket_cap(B)), st, b, k);
             });
             hipLaunchKernelGGL(kb_kick, g(kClsParticle), blk, 0, st, b, k);
         }

@@ -9,6 +9,12 @@ record that bench.py reads.
       what the same counter reads for the plain device copy of copy_bytes in
       the same run (the largest copy dispatch), as bytes per launch.
 
+  python -m paper_1401_4350_amd.prof counters <out.md> "<command>" "<kernel>|<kernel>..." <dir>...
+      per-dispatch means of every counter found in the pmc output folders,
+      for the dispatches of each named kernel at its largest grid (the
+      full-size launches), with the resources of the dispatch (VGPRs, LDS)
+      and a few ratios derived from them.
+
 The traffic record carries a hash of the kernel sources; bench.py uses it
 only while the sources are unchanged.
 """
@@ -81,6 +87,81 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int) -> dic
     return out
 
 
+def counters_markdown(dirs: list[str], kernels: list[str], command: str) -> str:
+    """Mean value per dispatch of each counter, per kernel, from one or more
+    rocprofv3 --pmc folders.  A kernel is every full name that contains the
+    given text, at its largest grid (the full-size launches); dispatches that
+    took less than half the longest one of that kernel and grid are left out
+    (launches that return at once when no list rebuild is due)."""
+    rows = []
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows.extend(csv.DictReader(open(f)))
+
+    def dur(r):
+        return int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+
+    out = [f"Command: `{command}`", "",
+           "Mean per dispatch over the full-length dispatches of the kernel at its largest "
+           "grid (each pass is its own run; the counters of one dispatch come from one pass).",
+           ""]
+    for k in kernels:
+        groups: dict[tuple[str, int], list[dict]] = {}
+        for r in rows:
+            if k in r["Kernel_Name"]:
+                groups.setdefault((r["Kernel_Name"], int(r.get("Grid_Size", 0) or 0)), []).append(r)
+        if not groups:
+            out.append(f"## `{k}`: no dispatch found\n")
+            continue
+        names = sorted({name for name, _ in groups})
+        for name in names:
+            grid = max(g for nm, g in groups if nm == name)
+            sel = groups[(name, grid)]
+            longest = {}
+            for r in sel:  # per pass (a counter set), the longest dispatch
+                longest[r["Counter_Name"]] = max(longest.get(r["Counter_Name"], 0), dur(r))
+            vals: dict[str, list[float]] = {}
+            for r in sel:
+                if dur(r) >= 0.5 * longest[r["Counter_Name"]]:
+                    vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            r = sel[0]
+            out.append(f"## `{name[:100]}`")
+            out.append("")
+            out.append(f"grid {grid} threads, workgroup {r['Workgroup_Size']}, LDS "
+                       f"{r['LDS_Block_Size']} B, VGPR {r['VGPR_Count']} (+{r['Accum_VGPR_Count']} "
+                       f"AGPR), SGPR {r['SGPR_Count']}")
+            out.append("")
+            out.append("| counter | mean per dispatch | dispatches |")
+            out.append("|---|---:|---:|")
+            m = {c: sum(v) / len(v) for c, v in vals.items()}
+            for c in sorted(m):
+                out.append(f"| {c} | {m[c]:.6g} | {len(vals[c])} |")
+            derived = []
+            if m.get("SQ_ACTIVE_INST_LDS") and "SQ_LDS_BANK_CONFLICT" in m:
+                derived.append(("LDS bank-conflict cycles / LDS active cycles",
+                                m["SQ_LDS_BANK_CONFLICT"] / m["SQ_ACTIVE_INST_LDS"]))
+            if m.get("SQ_WAVE_CYCLES"):
+                for c, what in (("SQ_WAIT_INST_ANY", "waiting on a dependency"),
+                                ("SQ_ACTIVE_INST_VALU", "issuing VALU"),
+                                ("SQ_ACTIVE_INST_LDS", "issuing LDS"),
+                                ("SQ_WAIT_INST_LDS", "waiting on LDS")):
+                    if c in m:
+                        derived.append((f"{c} / SQ_WAVE_CYCLES ({what})", m[c] / m["SQ_WAVE_CYCLES"]))
+            if m.get("SQ_WAVES"):
+                for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_SALU",
+                          "SQ_INSTS_LDS_ATOMIC"):
+                    if c in m:
+                        derived.append((f"{c} per wave", m[c] / m["SQ_WAVES"]))
+            if derived:
+                out.append("")
+                out.append("| derived | value |")
+                out.append("|---|---:|")
+                for nm, v in derived:
+                    out.append(f"| {nm} | {v:.4g} |")
+            out.append("")
+    return "\n".join(out) + "\n"
+
+
 def write_record(path: str, rec: dict, command: str):
     with open(path, "w") as f:
         f.write(f"command: {command}\n")
@@ -106,6 +187,9 @@ def main(argv):
         rec = traffic(argv[1], argv[2], argv[3], int(argv[4]))
         write_record(argv[5], rec, argv[6])
         print(rec)
+    elif argv[0] == "counters":
+        with open(argv[1], "w") as f:
+            f.write(counters_markdown(argv[4:], argv[3].split("|"), argv[2]))
     else:
         raise SystemExit(__doc__)
 
