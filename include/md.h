@@ -375,6 +375,48 @@ void md_batch_destroy(md_batch* b);
 /* Description of the last error on this batch ("" if none). */
 const char* md_batch_last_error(const md_batch* b);
 
+/* ---- Without device allocation ---------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * md_forces_static computes what md_create + md_set_state + md_build_cells +
+ * md_build_neighbors + md_forces compute (the same kernels), for coordinates
+ * already on the device and with no workspace argument: the particle
+ * records, cell lists and Verlet lists live in a static device array of the
+ * library, MD_STATIC_SCRATCH_BYTES per GPU, which each GPU the library runs
+ * on holds from the first call there until the process ends.  Nothing is
+ * allocated (no hipMalloc, no host-side buffers); the call only enqueues
+ * kernels on hip_stream (NULL = default stream) and returns.
+ *
+ *   d_x       device, n*3 doubles, positions in the caller's order (wrapped
+ *             into [0, box) as md_set_state wraps them); read only
+ *   d_q       device, n*4 doubles, quaternions (w, x, y, z), normalised on
+ *             load; required for MD_POT_PATCHY, ignored for LJ
+ *   d_f       device, n*3 doubles: forces in the caller's order (written)
+ *   d_torque  device, n*3 doubles: torques (MD_POT_PATCHY; ignored for LJ)
+ *   mode      any md_mode md_forces takes (MD_MODE_EDGE_DET needs edge_store)
+ *   d_status  device int32 or NULL: receives MD_OK, MD_ERR_NEIGHBOR_OVERFLOW
+ *             or MD_ERR_NONFINITE (non-finite or zero-norm input, or a
+ *             non-finite force) once the call's kernels have run
+ *
+ * Host-detected errors, returned before anything is enqueued:
+ * MD_ERR_INVALID_ARG / MD_ERR_BOX_TOO_SMALL as md_query_sizes, a missing
+ * pointer, an unknown mode, a cell order other than the two row-major ones;
+ * MD_ERR_BUFFER_TOO_SMALL if the system needs more than
+ * MD_STATIC_SCRATCH_BYTES: it needs state_bytes + workspace_bytes of
+ * md_query_sizes (an LJ fluid at rho = 0.8 with max_neighbors 208 about
+ * 1.8 kB per particle, so up to about 35 000 particles).  MD_ERR_HIP if a
+ * launch fails.
+ *
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents: calls that overlap on a GPU (other streams, other host
+ * threads) race and must be serialised by the caller.  Async. */
+#define MD_STATIC_SCRATCH_BYTES (64ull << 20)
+
+md_status md_forces_static(const md_params* p, const double* d_x, const double* d_q,
+                           double* d_f, double* d_torque, int32_t mode, int32_t* d_status,
+                           void* hip_stream);
+
 /* Static description of a status code. */
 const char* md_status_str(int32_t status);
 

@@ -8,6 +8,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -483,6 +484,88 @@ md_status md_create(const md_params* p, void* d_state, uint64_t state_bytes, voi
     if ((uintptr_t)d_state % kAlign || (uintptr_t)d_workspace % kAlign)
         return MD_ERR_BUFFER_TOO_SMALL;
     return create_system(p, L, d_state, d_workspace, hip_stream, out);
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// md_forces_static: the forces of md_forces for coordinates already on the
+// device, with no caller workspace.  State and workspace live in `scratch`,
+// a file-scope device array that every GPU the library runs on holds once
+// until the process ends.  Host code never uses the array's name as an
+// address (on the host it is only a stand-in for the symbol): the device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current, and only that address reaches the kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[MD_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+md_status static_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MD_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MD_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+md_status md_forces_static(const md_params* p, const double* d_x, const double* d_q,
+                           double* d_f, double* d_torque, int32_t mode, int32_t* d_status,
+                           void* hip_stream) {
+    md_status st = validate(p);
+    if (st != MD_OK) return st;
+    // state and workspace back to back, as md_query_sizes reports them
+    const Layout L = layout(*p);
+    if (L.state_bytes + L.ws_bytes > MD_STATIC_SCRATCH_BYTES) return MD_ERR_BUFFER_TOO_SMALL;
+    const bool patchy = p->pot == MD_POT_PATCHY;
+    if (!d_x || !d_f || (patchy && (!d_q || !d_torque))) return MD_ERR_INVALID_ARG;
+    if (mode != MD_MODE_VERTEX && mode != MD_MODE_EDGE && mode != MD_MODE_NEWTON &&
+        mode != MD_MODE_EDGE_DET)
+        return MD_ERR_INVALID_ARG;
+    if (mode == MD_MODE_EDGE_DET && !p->edge_store) return MD_ERR_INVALID_ARG;
+    // the curve orders need a host-built rank table uploaded per call
+    if (p->cell_order != MD_CELLS_ROW_MAJOR && p->cell_order != MD_CELLS_ROW_MAJOR_GATHER)
+        return MD_ERR_INVALID_ARG;
+    void* base = nullptr;
+    st = static_scratch(&base);
+    if (st != MD_OK) return st;
+    md::Sys y;
+    int edge_grid = 1;
+    fill_sys(p, L, base, (char*)base + L.state_bytes, y, &edge_grid);
+    hipStream_t s = (hipStream_t)hip_stream;
+    // The array keeps the previous call's contents, possibly of another
+    // layout: clear what the passes expect at zero (cell counts, completion
+    // counters and the control block, Newton replicas) with fill kernels.
+    hipError_t e = md::launch_fill_zero(y.ccount, L.ncell, s);
+    if (e == hipSuccess && y.nrep > 0)
+        e = md::launch_fill_zero((int*)y.rep, (long long)(patchy ? 16 : 8) * p->n * y.nrep, s);
+    if (e == hipSuccess) e = md::launch_clear_ctrl(y, s);
+    if (e == hipSuccess) e = md::launch_load_records(y, d_x, patchy ? d_q : nullptr, s);
+    // md_build_cells, md_build_neighbors, md_forces
+    if (e == hipSuccess) e = md::launch_set_rebuild(y, s);
+    if (e == hipSuccess) e = md::launch_rebuild(y, s, true, false);
+    if (e == hipSuccess) e = md::launch_rebuild(y, s, false, true);
+    if (e == hipSuccess) e = md::launch_clear_rebuild(y, s);
+    if (e == hipSuccess) e = md::launch_forces(y, mode, p->prec, false, s, edge_grid);
+    if (e == hipSuccess) e = md::launch_store_results(y, d_f, patchy ? d_torque : nullptr, s);
+    if (e == hipSuccess && d_status)
+        e = md::launch_status(y, d_status, MD_ERR_NEIGHBOR_OVERFLOW, MD_ERR_NONFINITE, s);
+    return e == hipSuccess ? MD_OK : MD_ERR_HIP;
 }
 
 

@@ -260,6 +260,16 @@ hipError_t launch_clear_rebuild(const Sys& s, hipStream_t st);
 hipError_t launch_thermostat(const Sys& s, double sv, double sl, double prob, uint64_t seed,
                              uint64_t counter, hipStream_t st);
 
+// md_forces_static: zero n ints (a fill kernel, no memset node); load the
+// caller's device coordinates (and quaternions) into the slot records; store
+// forces (and torques, if t is not null) back in original order; write the
+// sticky error of the call (or 0) to *out.
+hipError_t launch_fill_zero(int* p, long long n, hipStream_t st);
+hipError_t launch_load_records(const Sys& s, const double* x, const double* q, hipStream_t st);
+hipError_t launch_store_results(const Sys& s, double* f, double* t, hipStream_t st);
+hipError_t launch_status(const Sys& s, int* out, int overflow_code, int nonfinite_code,
+                         hipStream_t st);
+
 // Fills the potential constants of s from the physical parameters.
 void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, double w,
                    double delta, double rpc, int patch_model);

@@ -2887,6 +2887,98 @@ hipError_t launch_energy(const Sys& s, int prec, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Forces of coordinates that are already on the device, in one call with no
+// caller workspace (md_forces_static): the caller's original-order arrays are
+// loaded into the slot records (wrapped into [0, L) as md_set_state wraps
+// them), and the slot-order results are stored back in original order.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero(int* p, long long n) {
+    const long long stride = (long long)gridDim.x * kBlock;
+    for (long long k = (long long)blockIdx.x * kBlock + threadIdx.x; k < n; k += stride) p[k] = 0;
+}
+
+// Non-finite or zero input raises ctrl->nonfinite; the record then holds a
+// finite stand-in (the origin, the identity rotation) so that every later
+// index computation stays in range.
+__global__ __launch_bounds__(kBlock) void k_load_records(Sys s, const double* x, const double* q) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    bool ok = true;
+    double c[3];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        double y = x[3 * (size_t)i + k];
+        ok = ok && isfinite(y);
+        y -= s.box * floor(y / s.box);
+        if (y >= s.box) y -= s.box;
+        if (y < 0) y += s.box;
+        c[k] = isfinite(y) ? y : 0.0;
+    }
+    const double4 zero = make_double4(0.0, 0.0, 0.0, 0.0);
+    s.pos[i] = make_double4(c[0], c[1], c[2], 0.0);
+    s.vel[i] = zero;
+    s.frc[i] = zero;
+    s.id[i] = i;
+    if (s.pot != 0) {
+        const double* a = q + 4 * (size_t)i;
+        const double nn = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + a[3] * a[3]);
+        const bool qok = nn > 0 && isfinite(nn);
+        ok = ok && qok;
+        s.quat[i] = qok ? make_double4(a[0] / nn, a[1] / nn, a[2] / nn, a[3] / nn)
+                        : make_double4(1.0, 0.0, 0.0, 0.0);
+        s.angm[i] = zero;
+        s.trq[i] = zero;
+    }
+    if (!ok) atomicOr(&s.ctrl->nonfinite, 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_store_results(Sys s, double* f, double* t) {
+    const int a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= s.n) return;
+    const size_t i = (size_t)s.id[a];
+    const double4 F = s.frc[a];
+    f[3 * i] = F.x;
+    f[3 * i + 1] = F.y;
+    f[3 * i + 2] = F.z;
+    if (t) {
+        const double4 T = s.trq[a];
+        t[3 * i] = T.x;
+        t[3 * i + 1] = T.y;
+        t[3 * i + 2] = T.z;
+    }
+}
+
+// *out = 0, or the status code of the sticky device error of the call.
+__global__ void k_status(const Ctrl* c, int* out, int overflow_code, int nonfinite_code) {
+    *out = c->overflow ? overflow_code : (c->nonfinite ? nonfinite_code : 0);
+}
+
+hipError_t launch_fill_zero(int* p, long long n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const long long blocks = std::min((n + kBlock - 1) / kBlock, 4096LL);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(kBlock), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_records(const Sys& s, const double* x, const double* q, hipStream_t st) {
+    hipLaunchKernelGGL(k_load_records, grid_n(s.n), dim3(kBlock), 0, st, s, x, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_store_results(const Sys& s, double* f, double* t, hipStream_t st) {
+    hipLaunchKernelGGL(k_store_results, grid_n(s.n), dim3(kBlock), 0, st, s, f, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_status(const Sys& s, int* out, int overflow_code, int nonfinite_code,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_status, dim3(1), dim3(1), 0, st, s.ctrl, out, overflow_code,
+                       nonfinite_code);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Batched step.  The kernels below run the same bodies as the single-system
 // kernels, one system per block: block b of a kernel of class C serves
 // (slot, block) = map[C][b].  Idle blocks and slots whose steps for this

@@ -115,7 +115,11 @@ _SIGS = {
     "md_batch_info": ([_bat_p, ctypes.POINTER(MDBatchInfo)], ctypes.c_int),
     "md_batch_destroy": ([_bat_p], None),
     "md_batch_last_error": ([_bat_p], ctypes.c_char_p),
+    "md_forces_static": ([ctypes.POINTER(MDParams), _P, _P, _P, _P, ctypes.c_int32, _P, _P],
+                         ctypes.c_int),
 }
+# MD_STATIC_SCRATCH_BYTES of include/md.h
+STATIC_SCRATCH_BYTES = 64 << 20
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
@@ -172,6 +176,38 @@ def query_sizes(p: MDParams) -> MDSizes:
     if st != MD_OK:
         raise MDError(st, "md_query_sizes")
     return s
+
+
+def forces_static(params: MDParams, x: torch.Tensor, q: torch.Tensor | None = None,
+                  mode: str = "vertex", stream: torch.cuda.Stream | None = None):
+    """md_forces_static: forces (and torques) of the device coordinates x
+    (n x 3 float64 on the current device; q n x 4 for patchy) with no
+    workspace.  The outputs and the status word are allocated here, by the
+    caller's side; the call itself allocates nothing.  Returns
+    (f, torque or None, status tensor); the status holds MD_OK or a device
+    error code once the stream has run the call."""
+    n = params.n
+    dev = torch.device("cuda", torch.cuda.current_device())
+    patchy = params.pot == POT["patchy"]
+    for name, a, cols in (("x", x, 3), ("q", q, 4)):
+        if a is None:
+            continue
+        if a.dtype != torch.float64 or a.device != dev or tuple(a.shape) != (n, cols) \
+                or not a.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous ({n}, {cols}) float64 tensor on {dev}")
+    f = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    t = torch.empty((n, 3), dtype=torch.float64, device=dev) if patchy else None
+    status = torch.full((1,), -100, dtype=torch.int32, device=dev)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    st = _lib.md_forces_static(ctypes.byref(params), ctypes.c_void_p(x.data_ptr()),
+                               ctypes.c_void_p(q.data_ptr() if q is not None else 0),
+                               ctypes.c_void_p(f.data_ptr()),
+                               ctypes.c_void_p(t.data_ptr() if t is not None else 0),
+                               MODE[mode], ctypes.c_void_p(status.data_ptr()),
+                               ctypes.c_void_p(s.cuda_stream))
+    if st != MD_OK:
+        raise MDError(st, "md_forces_static")
+    return f, t, status
 
 
 class System:

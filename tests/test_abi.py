@@ -153,3 +153,30 @@ def test_batch_null_handle_calls(md):
     assert lib.md_batch_sync(None) == -1
     assert lib.md_batch_last_error(None).decode() == ""
     lib.md_batch_destroy(None)
+
+
+def test_forces_static_rejects_on_host(md):
+    """md_forces_static checks its arguments before any HIP call: bad
+    parameters, a system larger than the static array, missing pointers, an
+    unknown mode, the deterministic edge mode without edge_store, a curve
+    cell order.  Fake non-null pointers are never dereferenced on these
+    paths."""
+    from paper_1401_4350_amd.inputs import WORKLOADS
+    f = md.lib().md_forces_static
+    fake = ctypes.c_void_p(256)
+
+    def call(p, x=fake, q=fake, out=fake, t=fake, mode=0):
+        return f(ctypes.byref(p), x, q, out, t, mode, None, None)
+
+    assert call(_params(md, n=1)) == -1
+    assert call(_params(md, box=5.0)) == -5
+    big = md.make_params(WORKLOADS["lj_many"].with_(n=50000))
+    assert call(big) == -2
+    assert call(_params(md), x=None) == -1
+    assert call(_params(md), out=None) == -1
+    assert call(_params(md), mode=7) == -1
+    assert call(_params(md), mode=3) == -1  # edge_store = 0
+    assert call(_params(md, cell_order=2)) == -1
+    patchy = md.make_params(WORKLOADS["patchy"].with_(n=500))
+    assert call(patchy, q=None) == -1
+    assert call(patchy, t=None) == -1
