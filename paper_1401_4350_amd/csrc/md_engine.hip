@@ -161,6 +161,11 @@ void list_test_band(double box, double rv, float* lo, float* band) {
     *band = std::nextafter((float)(rv2 + 2.0 * e - (double)*lo), INFINITY);
 }
 
+// Rows of four 32-bit entries per particle in the tiled full list: room for
+// max_neighbors entries, and at least two rows (16 entries of 16 bits), the
+// padding a staged tile's lists get.
+uint64_t list_rows(int32_t max_neighbors) { return std::max<uint64_t>((max_neighbors + 3) / 4, 2); }
+
 Layout layout(const md_params& p) {
     Layout L;
     uint64_t n = (uint64_t)p.n;
@@ -209,7 +214,7 @@ Layout layout(const md_params& p) {
     L.ccount = take(cur, 4 * (uint64_t)L.ncell);
     L.cstart = take(cur, 4 * ((uint64_t)L.ncell + 1));
     L.order = take(cur, 4 * n);
-    L.nbr = take(cur, 4 * ((uint64_t)L.ntiles * ((p.max_neighbors + 3) / 4) + md::kListPadRows) *
+    L.nbr = take(cur, 4 * ((uint64_t)L.ntiles * list_rows(p.max_neighbors) + md::kListPadRows) *
                           md::kTile * 4);
     L.ncount = take(cur, 4 * n);
     L.hcount = take(cur, 4 * n);
@@ -227,7 +232,7 @@ Layout layout(const md_params& p) {
     // patchy) and an edge index per full-list entry
     const uint64_t nrec = p.pot == MD_POT_LJ ? 1 : 3;
     L.ef = take(cur, p.edge_store ? 32 * nrec * (uint64_t)L.max_half : 0);
-    L.eidx = take(cur, p.edge_store ? 4 * (uint64_t)L.ntiles * ((p.max_neighbors + 3) / 4) * md::kTile * 4 : 0);
+    L.eidx = take(cur, p.edge_store ? 4 * (uint64_t)L.ntiles * list_rows(p.max_neighbors) * md::kTile * 4 : 0);
     L.sync = take(cur, 4 * (uint64_t)md::kSyncUses * md::kSyncInts);
     L.tile_seg = take(cur, 16 * (uint64_t)L.ntiles * md::kSegMax);
     L.tile_nseg = take(cur, 4 * (uint64_t)L.ntiles);
@@ -357,7 +362,7 @@ void fill_sys(const md_params* p, const Layout& L, void* d_state, void* d_worksp
     y.nc = L.nc;
     y.ncell = L.ncell;
     y.cap = p->max_neighbors;
-    y.mcap = (p->max_neighbors + 3) / 4;
+    y.mcap = (int)list_rows(p->max_neighbors);
     y.pot = p->pot;
     y.nblk = L.nblk;
     y.max_half = L.max_half;

@@ -56,6 +56,7 @@ enum SyncUse { kSyncBin = 0, kSyncBuild, kSyncHalf, kSyncCol, kSyncUses };
 template <typename R>
 struct LJc {
     R sig2, eps4, eps24, rc2, vshift;
+    R c12, c6;  // 48 eps sigma^12 and 24 eps sigma^6: F/r = r^-2 r^-6 (c12 r^-6 - c6)
 };
 
 template <typename R>
@@ -72,7 +73,7 @@ struct Sys {
     int nc;         // cells per side
     int ncell;      // nc^3
     int cap;        // full-list capacity per particle
-    int mcap;       // ceil(cap / 4): rows of four entries per particle
+    int mcap;       // max(ceil(cap / 4), 2): rows of four 32-bit entries per particle
     int pot;        // 0 LJ, 1 patchy
     int nblk;       // ceil(n / kBlock)
     long long max_half;  // half-list capacity (entries)

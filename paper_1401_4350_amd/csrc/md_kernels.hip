@@ -1062,18 +1062,41 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
             }
         }
     }
-    if (act && (min(count, cap) & (nseg >= 0 ? 7 : 3)))  // last, partial row
-        *wrow = nseg >= 0 ? make_int4(w0, w1, w2, w3) : make_int4(e0, e1, e2, 0);
-    if (act) {
-        s.ncount[i] = count < cap ? count : cap;
-        s.hcount[i] = half;
-        if (count > cap) atomicOr(&s.ctrl->overflow, 1);
-    }
     // wavefront (= tile) totals: longest list and half-list length
     int mx = act ? count : 0, hs = act ? half : 0;
     for (int off = kWave / 2; off > 0; off >>= 1) {
         mx = max(mx, __shfl_xor(mx, off));
         hs += __shfl_xor(hs, off);
+    }
+    if (nseg >= 0) {
+        // Staged tile: every list is padded with the padding slot up to the
+        // tile's longest list rounded up to 16 entries, so the vertex pass
+        // reads whole rows without masking what lies past a list's end.
+        // (A particle's rows hold 8 * mcap >= 16 entries, mcap >= 2.)
+        const int bound = min((min(mx, cap) + 15) & ~15, 8 * s.mcap);
+        const int pad = s.lds_cap;
+        if (act) {
+            for (int c = min(count, cap); c < bound; c++) {
+                const int sl = c & 7, wd = sl >> 1;
+                const bool hi = sl & 1;
+                const int v = hi ? pad << 16 : pad;
+                w0 = wd == 0 ? (hi ? w0 | v : v) : w0;
+                w1 = wd == 1 ? (hi ? w1 | v : v) : w1;
+                w2 = wd == 2 ? (hi ? w2 | v : v) : w2;
+                w3 = wd == 3 ? (hi ? w3 | v : v) : w3;
+                if (sl == 7) {
+                    *wrow = make_int4(w0, w1, w2, w3);
+                    wrow += kTile;
+                }
+            }
+        }
+    } else if (act && (min(count, cap) & 3)) {  // last, partial row
+        *wrow = make_int4(e0, e1, e2, 0);
+    }
+    if (act) {
+        s.ncount[i] = count < cap ? count : cap;
+        s.hcount[i] = half;
+        if (count > cap) atomicOr(&s.ctrl->overflow, 1);
     }
     if (lane == 0 && tact) {  // read by the last workgroup
         coh_store(&s.tmax[tile], mx);
@@ -1354,6 +1377,23 @@ __device__ __forceinline__ void lj_walk_global(const Sys& s, int ii, int q, int 
 #endif
 constexpr int kPrefetch = MD_VERTEX_PREFETCH;  // list entries held in registers per lane
 
+// F/r of the LJ pair at separation^2 r2, exactly zero from r_c on: there the
+// high word of r2 is replaced by that of 1e300 (FP64; 1e30 in FP32), whose
+// inverse cubed underflows to zero.  F/r = r^-2 u (c12 u - c6), u = r^-6.
+__device__ __forceinline__ double lj_fr_cut(const Sys& s, double r2) {
+    const bool in = r2 < s.rc2;
+    const double r2m = __hiloint2double(in ? __double2hiint(r2) : 0x7E37E43C, __double2loint(r2));
+    const double inv = rcp_nr(r2m);
+    const double u = inv * inv * inv;
+    return inv * u * fma(s.l64.c12, u, -s.l64.c6);
+}
+__device__ __forceinline__ float lj_fr_cut32(const Sys& s, double r2) {
+    const float r2f = r2 < s.rc2 ? (float)r2 : 1e30f;
+    const float inv = rcp_nr(r2f);
+    const float u = inv * inv * inv;
+    return inv * u * fmaf(s.l32.c12, u, -s.l32.c6);
+}
+
 // Branch-free LJ term from an LDS image that already carries the periodic
 // image.  The cut-off selects a 0/1 factor, so every lane runs the same
 // instruction stream.
@@ -1365,6 +1405,16 @@ __device__ __forceinline__ void lj_pos_term(const Sys& s, double px, double py, 
     double dy = py - xi.y;
     double dz = pz - xi.z;
     double r2 = dx * dx + dy * dy + dz * dz;
+    if (!ENERGY) {
+        if (PREC == 0) {
+            const double fr = lj_fr_cut(s, r2);
+            f.add(-fr * dx, -fr * dy, -fr * dz);
+        } else {
+            const float fr = lj_fr_cut32(s, r2);
+            f.add(-fr * (float)dx, -fr * (float)dy, -fr * (float)dz);
+        }
+        return;
+    }
     bool in = r2 < s.rc2;
     if (PREC == 0) {
         double inv = rcp_nr(r2);
@@ -1440,16 +1490,16 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
         static_assert(TPP == 4 && kTile * TPP == kBlock, "word offset 256 m + tid");
         static_assert(E % 2 == 0 && E / 2 <= kListPadRows, "prefetch beyond the spare rows");
         const int* lane_rows = s.nbr + (size_t)tile * s.mcap * (kTile * 4) + threadIdx.x;
+        // The list build pads a staged tile's lists with the padding slot up
+        // to the tile's longest list rounded up to 16 entries, which covers
+        // every group of four lane entries below mmax: no masking here.
         auto load_block = [&](int n0, int (&en)[E]) {
             const int* bp = lane_rows + (size_t)(n0 >> 1) * (kTile * 4);
 #pragma unroll
             for (int m = 0; m < E / 2; m++) {
                 const int v = __builtin_nontemporal_load(bp + m * (kTile * 4));
-                // past the end: all index bits set, clamped to the padding
-                // slot; the value depends on the load either way, so the
-                // compiler cannot move the load under a branch
-                en[2 * m] = min((v & 0xffff) | (n0 + 2 * m < mine ? 0 : 0xffff), cap);
-                en[2 * m + 1] = min((int)((unsigned)v >> 16) | (n0 + 2 * m + 1 < mine ? 0 : 0xffff), cap);
+                en[2 * m] = v & 0xffff;
+                en[2 * m + 1] = (int)((unsigned)v >> 16);
             }
         };
         // groups of four: the four records are read from LDS before the
@@ -1461,10 +1511,10 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
                     double px[4], py[4], pz[4];
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
-                        const double* p = lds3 + 3 * en[m + u];
-                        px[u] = p[0];
-                        py[u] = p[1];
-                        pz[u] = p[2];
+                        const unsigned a = 3u * (unsigned)en[m + u];
+                        px[u] = lds3[a];
+                        py[u] = lds3[a + 1];
+                        pz[u] = lds3[a + 2];
                     }
 #pragma unroll
                     for (int u = 0; u < 4; u++) lj_pos_term<PREC, ENERGY>(s, px[u], py[u], pz[u], xi, f, e, w);
@@ -1505,7 +1555,10 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
         s.wpart[i] = w;
         return;
     }
-    s.frc[i] = make_double4(fx, fy, fz, 0.0);
+    // The fused step (DRIFT) keeps its forces in registers: nothing reads
+    // them before the next force pass (the last step of md_step is never a
+    // fused one and stores them).
+    if (!DRIFT) s.frc[i] = make_double4(fx, fy, fz, 0.0);
     if (!isfinite(fx + fy + fz)) atomicOr(&s.ctrl->nonfinite, 1);
     if (KICK) {
         double4 v = s.vel[i];
@@ -2626,9 +2679,11 @@ void set_potential(Sys& s, double eps, double sigma, double rc, double eps_p, do
     double s2 = sigma * sigma / (rc * rc);
     double s6 = s2 * s2 * s2;
     double vs = 4.0 * eps * (s6 * s6 - s6);
-    s.l64 = {sigma * sigma, 4.0 * eps, 24.0 * eps, rc * rc, vs};
+    const double sig6 = sigma * sigma * sigma * sigma * sigma * sigma;
+    s.l64 = {sigma * sigma, 4.0 * eps, 24.0 * eps, rc * rc, vs, 48.0 * eps * sig6 * sig6,
+             24.0 * eps * sig6};
     s.l32 = {(float)(sigma * sigma), (float)(4.0 * eps), (float)(24.0 * eps), (float)(rc * rc),
-             (float)vs};
+             (float)vs, (float)(48.0 * eps * sig6 * sig6), (float)(24.0 * eps * sig6)};
     double wca2 = cbrt(2.0) * sigma * sigma;
     double rpc2 = rpc > 0 ? rpc * rpc : 0.0;
     s.p64 = {sigma * sigma, 4.0 * eps, 24.0 * eps, eps, wca2, eps_p, 1.0 / (w * w), delta, rpc2,
