@@ -734,11 +734,18 @@ __device__ __forceinline__ void region_issue(const Sys& s, const double4* src, i
     constexpr int W = kBlock / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
+    // every descriptor load first (the index clamped into the tile's table
+    // instead of a branch per load, so the loads issue together and are
+    // waited for once), then every record load
+    const int last = max(nchk - 1, 0);
+#pragma unroll
+    for (int r = 0; r < RegionBatch::R; r++) b.d[r] = chk[min(c0 + r * W, last)];
 #pragma unroll
     for (int r = 0; r < RegionBatch::R; r++) {
-        int c = c0 + r * W;
-        b.d[r] = c < nchk ? chk[c] : make_int4(0, 1, 0, -1);
-        // unconditional load (lanes past the chunk end re-read its last slot)
+        // a chunk past the end re-reads the last one and is not stored (its
+        // descriptor still feeds the address, so its load cannot move under
+        // a branch); lanes past a chunk's end re-read its last slot
+        if (c0 + r * W >= nchk) b.d[r].w = -1;
         b.p[r] = src[b.d[r].x + min(lane, b.d[r].y - b.d[r].x - 1)];
     }
 }
