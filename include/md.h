@@ -44,7 +44,8 @@
  *   - Every function returns md_status; nothing aborts or throws across the ABI.
  *     Argument errors are detected on the host before any HIP call.
  *   - Device buffers are owned by the caller (see md_create); libmd owns only the
- *     handle and a few bytes of host state.  libmd never calls hipMalloc.
+ *     handle and a few bytes of host state (for md_step, 64 pinned bytes).
+ *     libmd never calls hipMalloc.
  *   - Work is enqueued on the caller's HIP stream.  Functions marked "async"
  *     return before the GPU finishes; functions marked "syncs" wait for the
  *     stream and report sticky device-side errors (list overflow, non-finite
@@ -211,9 +212,15 @@ md_status md_forces(md_system* s, int32_t mode);
 
 /* nsteps velocity-Verlet steps (rotational velocity Verlet for patchy) with
  * forces from `mode`.  Per step: half kick, drift, wrap; if any particle moved
- * more than skin/2 since the last build the cells and lists are rebuilt on
- * the device (no host round trip); forces; half kick.  Computes forces first
- * if they are not valid.  Syncs at the end and reports device errors. */
+ * more than skin/2 since the last build the cells and lists are rebuilt;
+ * forces; half kick.  Computes forces first if they are not valid.  The
+ * vertex LJ mode runs a step as one launch (forces, both half kicks, drift)
+ * and enqueues these in small batches: a launch whose predecessor's drift
+ * asks for a rebuild does nothing, the host learns of it from a pinned word
+ * the launches write (allocated with hipHostMalloc on the first such call)
+ * and enqueues the rebuild before resuming.  The other modes run the rebuild
+ * test on the device every step.  Syncs at the end and reports device
+ * errors. */
 md_status md_step(md_system* s, int32_t nsteps, int32_t mode);
 
 /* The NVT thermostat of the Methods section, in the reading of the Brownian
@@ -290,9 +297,11 @@ void md_destroy(md_system* s);
  * for the whole batch, each block serving one block's worth of one system, so
  * small systems share the GPU instead of each paying the launch latency of a
  * full step.  The paper times single systems only (Results section); the
- * batch runs the same per-system arithmetic -- a system's vertex-mode
- * trajectory is bitwise the one md_step gives it alone, and an edge-mode one
- * differs only by the order of its atomic additions.
+ * batch runs the same per-system arithmetic -- a system's vertex-mode and
+ * deterministic-edge-mode trajectories are bitwise the ones md_step gives it
+ * alone, and an edge-mode one differs only by the order of its atomic
+ * additions.  The deterministic edge mode needs systems made with
+ * edge_store = 1 (md_batch_admit returns MD_ERR_INVALID_ARG otherwise).
  *
  * The batch keeps a device table of per-slot descriptors and, per block class
  * of the step, a map from grid block to (slot, block of that system).  Maps
@@ -310,7 +319,7 @@ typedef struct md_batch md_batch; /* opaque handle */
 
 typedef struct {
     int32_t max_systems;      /* slots, 1 .. 65536                                    */
-    int32_t mode;             /* md_mode of every step                                */
+    int32_t mode;             /* md_mode of every step: vertex, edge or edge_det     */
     int32_t steps_per_launch; /* steps in one launch, 1 .. 4096                        */
     int32_t use_graph;        /* 1: launch captured hipGraphs; 0: launch kernels      */
     int64_t max_particles;    /* bound on the sum of n over admitted systems          */
@@ -352,6 +361,14 @@ md_status md_batch_steps_left(const md_batch* b, int32_t slot, int64_t* left);
  * the slot.  Syncs; returns the system's own device status (list overflow,
  * non-finite forces) and leaves it usable by the single-system calls. */
 md_status md_batch_retire(md_batch* b, int32_t slot);
+
+/* md_thermostat for the system in `slot` while it is admitted: the same
+ * momentum refresh (same draws for the same seed and counter), enqueued on the
+ * batch stream after the steps launched so far and before the next
+ * md_batch_step.  Errors: a free slot, temperature < 0 or not finite, prob
+ * outside [0, 1] (MD_ERR_INVALID_ARG).  Async. */
+md_status md_batch_thermostat(md_batch* b, int32_t slot, double temperature, double prob,
+                              uint64_t seed, uint64_t counter);
 
 /* Waits for the batch stream. */
 md_status md_batch_sync(md_batch* b);

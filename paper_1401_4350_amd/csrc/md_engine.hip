@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -281,9 +282,47 @@ struct md_system {
     bool profiling = false;
     std::vector<hipEvent_t> events;  // 4 per step of the current md_step call
     md_profile_t prof{};
+    // fused vertex steps: launch ids, the host-mapped word in which every
+    // launch that runs leaves its id, and one event per batch in flight
+    int next_id = 2;
+    int* run_host = nullptr;
+    int* run_dev = nullptr;
+    hipEvent_t fev[2] = {nullptr, nullptr};
 
     ~md_system() {
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipEvent_t e : fev)
+            if (e) (void)hipEventDestroy(e);
+        if (run_host) (void)hipHostFree(run_host);
+    }
+    // A pinned, host-mapped word and two events, made on the first fused step.
+    hipError_t fused_setup() {
+        if (run_host) return hipSuccess;
+        void* h = nullptr;
+        hipError_t r = hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent);
+        if (r != hipSuccess) return r;
+        run_host = static_cast<int*>(h);
+        *run_host = 0;
+        void* d = nullptr;
+        r = hipHostGetDevicePointer(&d, h, 0);
+        if (r != hipSuccess) return r;
+        run_dev = static_cast<int*>(d);
+        for (hipEvent_t& e : fev) {
+            r = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+            if (r != hipSuccess) return r;
+        }
+        sys.host_run = run_dev;
+        return hipSuccess;
+    }
+    // Ids for the next n fused launches, consecutive from the returned one
+    // (they restart, with the request slots cleared, long before they could
+    // overflow).
+    hipError_t reserve_ids(int n) {
+        if (next_id + n < (1 << 30)) return hipSuccess;
+        char* req = reinterpret_cast<char*>(sys.ctrl) + offsetof(md::Ctrl, req);
+        hipError_t r = hipMemsetAsync(req, 0, sizeof(md::Ctrl::req), stream);
+        next_id = 2;
+        return r;
     }
     hipError_t ensure_events(size_t count) {
         while (events.size() < count) {
@@ -682,6 +721,102 @@ md_status md_forces(md_system* s, int32_t mode) {
     return MD_OK;
 }
 
+// Fused vertex LJ steps without the rebuild test chain in every step.  Each
+// fused launch (forces, closing and next half kick, drift) checks at its start
+// whether the drift of the launch before asked for a list rebuild, and if so
+// does nothing but pass the request on (Ctrl::req).  The host enqueues the
+// launches in batches of kFusedBatch, two batches ahead, and after each batch
+// reads the id of the last launch that ran (a host-mapped word): if a batch
+// stopped early, it waits for the rest, runs the rebuild chain on the
+// positions of the last launch that ran and resumes from there.  The four
+// launches of the chain (each of which returns at once when no rebuild is
+// due) then run only at rebuilds instead of in every step.  Same arithmetic,
+// same rebuild steps as the per-step sequence.
+constexpr int kFusedBatch = 4;
+
+static md_status step_fused(md_system* s, int nsteps) {
+    hipStream_t st = s->stream;
+    md::Sys y = s->sys;
+    double4* const pa = y.pos;
+    double4* const pb = y.pos_alt;
+    auto parity = [&](int ran) {  // the positions after `ran` fused launches
+        y.pos = (ran & 1) ? pb : pa;
+        y.pos_alt = (ran & 1) ? pa : pb;
+    };
+    auto fail = [&](hipError_t e, const char* where) {
+        s->sys = y;
+        return s->hip(e, where);
+    };
+    // step 0: half kick and drift, then the rebuild test chain
+    hipError_t e = md::launch_kick_drift(y, false, st);
+    if (e == hipSuccess) e = md::launch_rebuild(y, st, true, true);
+    if (e != hipSuccess) return fail(e, "step launch");
+    const int nfused = nsteps - 1;  // fused launches that must run
+    int done = 0;                   // of which known to have run
+    int issued = 0;                 // enqueued after those, not yet confirmed
+    struct Batch {
+        int first, n;
+    } q[2];
+    int head = 0, inflight = 0;
+    int stalls = 0;  // rebuilds in a row after which no launch ran
+    while (done < nfused) {
+        while (inflight < 2 && done + issued < nfused) {
+            const int k = (head + inflight) & 1;
+            const int n = std::min(kFusedBatch, nfused - done - issued);
+            e = s->reserve_ids(n);
+            if (e != hipSuccess) return fail(e, "fused step ids");
+            q[k].first = s->next_id;
+            q[k].n = n;
+            for (int j = 0; j < n; j++) {
+                y.launch_id = s->next_id++;
+                e = md::launch_vertex_kick_drift(y, s->p.prec, st);
+                if (e != hipSuccess) return fail(e, "fused step launch");
+                std::swap(y.pos, y.pos_alt);
+            }
+            e = hipEventRecord(s->fev[k], st);
+            if (e != hipSuccess) return fail(e, "fused step event");
+            issued += n;
+            inflight++;
+        }
+        e = hipEventSynchronize(s->fev[head]);
+        if (e != hipSuccess) return fail(e, "fused step wait");
+        const Batch b = q[head];
+        head ^= 1;
+        inflight--;
+        const int last = *(volatile int*)s->run_host;
+        const int ran = last >= b.first ? std::min(last - b.first + 1, b.n) : 0;
+        done += ran;
+        issued -= b.n;
+        stalls = ran > 0 ? 0 : stalls + 1;
+        if (stalls > 2) {  // a rebuild that does not let the next launch run: a bug, not a hang
+            s->sys = y;
+            return s->fail(MD_ERR_STATE, "internal: fused steps make no progress");
+        }
+        if (ran < b.n) {
+            // a rebuild is due: every later launch did nothing
+            if (inflight) {
+                e = hipEventSynchronize(s->fev[head]);
+                if (e != hipSuccess) return fail(e, "fused step wait");
+                issued -= q[head].n;
+                head ^= 1;
+                inflight = 0;
+            }
+            parity(done);
+            s->next_id++;  // not the successor of a launch that passed the request on
+            e = md::launch_rebuild(y, st, true, true);
+            if (e != hipSuccess) return fail(e, "rebuild launch");
+        }
+    }
+    parity(done);
+    // last step: the rebuild test chain, forces and the closing kick
+    e = md::launch_rebuild(y, st, true, true);
+    if (e == hipSuccess) e = md::launch_forces(y, MD_MODE_VERTEX, s->p.prec, true, st, s->edge_grid);
+    if (e != hipSuccess) return fail(e, "step launch");
+    s->sys = y;
+    s->steps += nsteps;
+    return s->sync_check();
+}
+
 md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     if (!s) return MD_ERR_INVALID_ARG;
     if (s->batch) return s->admitted();
@@ -697,11 +832,16 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
     // the second position buffer, whose role swaps with the first every
     // fused step), so after the first step one MD step is the rebuild test
     // chain and one force launch.
-    md::Sys y = s->sys;
     const bool fuse = mode == MD_MODE_VERTEX && s->p.pot == MD_POT_LJ;
+    bool prof = s->profiling;
+    if (fuse) {
+        md_status r = s->hip(s->fused_setup(), "fused step setup");
+        if (r != MD_OK) return r;
+        if (!prof && nsteps >= 2) return step_fused(s, nsteps);
+    }
+    md::Sys y = s->sys;
     // passes that add with atomics into the force array need it cleared first
     bool edge = mode == MD_MODE_EDGE || (mode == MD_MODE_NEWTON && s->sys.nrep == 0);
-    bool prof = s->profiling;
     constexpr size_t kEv = 5;  // events per profiled step
     if (prof) {
         md_status r = s->hip(s->ensure_events(kEv * (size_t)nsteps), "profile events");
@@ -716,6 +856,8 @@ md_status md_step(md_system* s, int32_t nsteps, int32_t mode) {
         if (e == hipSuccess) e = md::launch_rebuild(y, st, true, true);
         if (e == hipSuccess && prof) e = hipEventRecord(ev[2], st);
         if (fuse && k + 1 < nsteps) {
+            if (e == hipSuccess) e = s->reserve_ids(1);
+            y.launch_id = s->next_id++;
             if (e == hipSuccess) e = md::launch_vertex_kick_drift(y, s->p.prec, st);
             std::swap(y.pos, y.pos_alt);
             if (e == hipSuccess && prof) e = hipEventRecord(ev[3], st);
@@ -951,7 +1093,8 @@ struct BatchLayout {
 md_status validate_batch(const md_batch_params* p) {
     if (!p) return MD_ERR_INVALID_ARG;
     if (p->max_systems < 1 || p->max_systems > 65536) return MD_ERR_INVALID_ARG;
-    if (p->mode != MD_MODE_VERTEX && p->mode != MD_MODE_EDGE) return MD_ERR_INVALID_ARG;
+    if (p->mode != MD_MODE_VERTEX && p->mode != MD_MODE_EDGE && p->mode != MD_MODE_EDGE_DET)
+        return MD_ERR_INVALID_ARG;
     if (p->steps_per_launch < 1 || p->steps_per_launch > 4096) return MD_ERR_INVALID_ARG;
     if (p->use_graph != 0 && p->use_graph != 1) return MD_ERR_INVALID_ARG;
     if (p->max_particles < 2 || p->max_particles > (1LL << 30)) return MD_ERR_INVALID_ARG;
@@ -1253,6 +1396,8 @@ md_status md_batch_admit(md_batch* b, md_system* s, int64_t nsteps, int32_t* slo
     *slot = -1;
     if (s->batch) return b->fail(MD_ERR_STATE, "system already admitted to a batch");
     if (!s->lists_valid) return b->fail(MD_ERR_STATE, "system has no lists (md_build_neighbors)");
+    if (b->p.mode == MD_MODE_EDGE_DET && !s->p.edge_store)
+        return b->fail(MD_ERR_INVALID_ARG, "the deterministic edge mode needs edge_store = 1");
     int k = 0;
     while (k < b->p.max_systems && b->slot[k]) k++;
     if (k == b->p.max_systems) return b->fail(MD_ERR_BUFFER_TOO_SMALL, "no free slot");
@@ -1347,6 +1492,21 @@ md_status md_batch_retire(md_batch* b, int32_t slot) {
     r = b->upload();
     if (r != MD_OK) return r;
     return s->sync_check();
+}
+
+md_status md_batch_thermostat(md_batch* b, int32_t slot, double temperature, double prob,
+                              uint64_t seed, uint64_t counter) {
+    if (!b || slot < 0 || slot >= b->p.max_systems) return MD_ERR_INVALID_ARG;
+    md_system* s = b->slot[slot];
+    if (!s) return b->fail(MD_ERR_INVALID_ARG, "slot is free");
+    if (!std::isfinite(temperature) || !(temperature >= 0) || !(prob >= 0) || !(prob <= 1))
+        return b->fail(MD_ERR_INVALID_ARG, "thermostat needs temperature >= 0 and 0 <= prob <= 1");
+    const double sv = std::sqrt(temperature / s->p.mass);
+    const double sl = s->p.pot == MD_POT_PATCHY ? std::sqrt(s->p.inertia * temperature) : 0.0;
+    // the system's own arrays (the batch table holds its descriptor), on the
+    // batch stream: after the steps launched so far, before the next ones
+    return b->hip(md::launch_thermostat(b->h_tab[slot], sv, sl, prob, seed, counter, b->stream),
+                  "batch thermostat");
 }
 
 md_status md_batch_sync(md_batch* b) {

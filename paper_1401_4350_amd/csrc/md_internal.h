@@ -38,7 +38,12 @@ struct Ctrl {
     int half_stale;     // the half list predates the last build (filled on demand)
     int eidx_stale;     // the edge index of the full-list entries predates the half list
     long long nonzero;  // half-list entries with a non-zero pair result (md_stats)
-    long long pad1;
+    // Fused vertex steps (launch_vertex_kick_drift): a launch with id L whose
+    // drift finds a particle past half the skin stores L in req[L & 1]; the
+    // next launch, L + 1, does nothing if req[L & 1] == L (its lists would be
+    // stale) but store L + 1 in req[(L + 1) & 1], and so on until the host
+    // rebuilds and resumes with an id that skips one.
+    int req[2];
 };
 
 // Completion counters of the kernels whose last workgroup runs an epilogue
@@ -145,6 +150,8 @@ struct Sys {
     const int* cell_rank;  // curve orders: cell id of row-major cell (z * nc + y) * nc + x
     int eblk;        // blocks of the edge pass (grid-stride over the half list)
     int prec;        // md_precision of the pair maths
+    int launch_id;   // fused vertex steps: id of this launch (see Ctrl::req)
+    int* host_run;   // fused vertex steps: host-mapped word, gets the id of every launch that runs
 };
 
 constexpr int kRedBlocks = 1024;

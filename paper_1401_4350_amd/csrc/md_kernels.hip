@@ -337,6 +337,7 @@ __global__ void k_clear_ctrl(Ctrl* c, int* sync) {
     c->half_stale = 0;
     c->eidx_stale = 0;
     c->nonzero = 0;
+    c->req[0] = c->req[1] = 0;  // launch ids start at 2
 }
 
 // True in the one workgroup, of the nb that call this with the same counter,
@@ -825,6 +826,7 @@ __device__ __forceinline__ void scan_tiles(const Sys& s) {
         s.ctrl->half_stale = 1;
         s.ctrl->eidx_stale = s.estore;
         s.ctrl->rebuild = 0;  // every workgroup of the build has read it
+        s.ctrl->req[0] = s.ctrl->req[1] = 0;  // a requested rebuild is done
     }
 }
 
@@ -868,7 +870,9 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     const int cx = cell_coord(xi.x, s.cell_inv, nc);
     const int cy = cell_coord(xi.y, s.cell_inv, nc);
     const int cz = cell_coord(xi.z, s.cell_inv, nc);
-    int4* wrow = (int4*)list_row_w(s, ii);  // the particle's current row of four entries
+    // the particle's current row of four entries (slots past n in the last
+    // tile have rows of their own, which get the padding)
+    int4* wrow = (int4*)list_row_w(s, tact ? i : ii);
     const int cap = s.cap;
     const double rv2 = s.rv2;
     int count = 0, half = 0;
@@ -1082,7 +1086,7 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
         // (A particle's rows hold 8 * mcap >= 16 entries, mcap >= 2.)
         const int bound = min((min(mx, cap) + 15) & ~15, 8 * s.mcap);
         const int pad = s.lds_cap;
-        if (act) {
+        if (tact) {  // also the rows of slots past n, which the vertex pass reads
             for (int c = min(count, cap); c < bound; c++) {
                 const int sl = c & 7, wd = sl >> 1;
                 const bool hi = sl & 1;
@@ -1465,6 +1469,17 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     static_assert(!DRIFT || KICK, "the drift follows the closing kick");
     extern __shared__ double lds3[];
     const int tile = bid;
+    if (DRIFT) {
+        // a rebuild requested by the previous launch's drift (or passed on by
+        // a launch that did nothing for it): this launch does nothing either
+        const int prev = s.launch_id - 1;
+        if (s.ctrl->req[prev & 1] == prev) {
+            if (bid == 0 && threadIdx.x == 0) s.ctrl->req[s.launch_id & 1] = s.launch_id;
+            return;
+        }
+        if (bid == 0 && threadIdx.x == 0)
+            __hip_atomic_store(s.host_run, s.launch_id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
     const int i = tile * kTile + threadIdx.x / TPP;
     const int q = threadIdx.x % TPP;
     const int nseg = s.tile_nseg[tile];
@@ -1583,7 +1598,10 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
             s.pos_alt[i] = x;
             const double4 xb = s.xbuild[i];
             const double ddx = x.x - xb.x, ddy = x.y - xb.y, ddz = x.z - xb.z;
-            if (ddx * ddx + ddy * ddy + ddz * ddz > s.disp2) s.ctrl->rebuild = 1;
+            if (ddx * ddx + ddy * ddy + ddz * ddz > s.disp2) {
+                s.ctrl->rebuild = 1;
+                s.ctrl->req[s.launch_id & 1] = s.launch_id;
+            }
         }
         s.vel[i] = v;
     }
@@ -3111,6 +3129,34 @@ __global__ __launch_bounds__(kBlock) void kb_vertex(BatchDev b, int step) {
     });
 }
 
+// Deterministic edge mode: the edge indices of the full-list entries (after
+// the half list), the per-edge store pass (grid-stride over the system's
+// half list with the class's blocks) and the ordered gather.
+__global__ __launch_bounds__(kBlock) void kb_col_fill(BatchDev b, int step) {
+    batch_block<kClsTile>(b, step, [](const Sys& s, int lb) { b_col_fill(s, lb, s.ntiles); });
+}
+
+template <int C>
+__global__ __launch_bounds__(kBlock) void kb_edge_store(BatchDev b, int step) {
+    batch_block<C>(b, step, [](const Sys& s, int lb) {
+        const int nb = class_blocks(s, C);
+        if (s.pot == 0) {
+            if (s.prec == 0) b_edge<0, 0, true>(s, lb, nb);
+            else b_edge<0, 1, true>(s, lb, nb);
+        } else {
+            if (s.prec == 0) b_edge<1, 0, true>(s, lb, nb);
+            else b_edge<1, 1, true>(s, lb, nb);
+        }
+    });
+}
+
+__global__ __launch_bounds__(kBlock) void kb_edge_gather(BatchDev b, int step) {
+    batch_block<kClsTile>(b, step, [](const Sys& s, int lb) {
+        if (s.pot == 0) b_edge_gather<0>(s, lb, s.ntiles);
+        else b_edge_gather<1>(s, lb, s.ntiles);
+    });
+}
+
 template <int C>
 __global__ __launch_bounds__(kBlock) void kb_edge(BatchDev b, int step) {
     batch_block<C>(b, step, [](const Sys& s, int lb) {
@@ -3150,8 +3196,9 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
     };
     const size_t sh_map = sizeof(int) * (size_t)(kLdsCapMax + 8);
     for (int k = 0; k < steps; k++) {
-        if (mode == 0) hipLaunchKernelGGL(kb_kick_drift<false>, g(kClsParticle), blk, 0, st, b, k);
-        else hipLaunchKernelGGL(kb_kick_drift<true>, g(kClsParticle), blk, 0, st, b, k);
+        // the passes that add into F with atomics need it cleared
+        if (mode == 1) hipLaunchKernelGGL(kb_kick_drift<true>, g(kClsParticle), blk, 0, st, b, k);
+        else hipLaunchKernelGGL(kb_kick_drift<false>, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_cell_bin, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_cell_scatter, g(kClsParticle), blk, 0, st, b, k);
         hipLaunchKernelGGL(kb_sort_tiles, g(kClsSortTiles), blk, 0, st, b, k);
@@ -3163,6 +3210,16 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
                     hipLaunchKernelGGL(kb_vertex<kClsVertex0 + B>, g(kClsVertex0 + B), blk,
                                        lds_region_bytes(bucket_cap(B)), st, b, k);
             });
+        } else if (mode == 3) {  // deterministic edge: per-edge records, ordered gather
+            hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
+            hipLaunchKernelGGL(kb_col_fill, g(kClsTile), blk, sh_map, st, b, k);
+            per_bucket([&](auto bk) {
+                constexpr int B = decltype(bk)::value;
+                if (grid[kClsEdge0 + B] > 0)
+                    hipLaunchKernelGGL(kb_edge_store<kClsEdge0 + B>, g(kClsEdge0 + B), blk, 0, st, b, k);
+            });
+            hipLaunchKernelGGL(kb_edge_gather, g(kClsTile), blk, 0, st, b, k);
+            hipLaunchKernelGGL(kb_kick, g(kClsParticle), blk, 0, st, b, k);
         } else {
             hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
             per_bucket([&](auto bk) {
@@ -3188,7 +3245,13 @@ int batch_kernel_class(const void* func) {
     for (const void* f : particle)
         if (f == func) return kClsParticle;
     if (func == reinterpret_cast<const void*>(&kb_sort_tiles)) return kClsSortTiles;
-    if (func == reinterpret_cast<const void*>(&kb_half_fill)) return kClsTile;
+    if (func == reinterpret_cast<const void*>(&kb_half_fill) ||
+        func == reinterpret_cast<const void*>(&kb_col_fill) ||
+        func == reinterpret_cast<const void*>(&kb_edge_gather))
+        return kClsTile;
+    if (func == reinterpret_cast<const void*>(&kb_edge_store<kClsEdge0>)) return kClsEdge0;
+    if (func == reinterpret_cast<const void*>(&kb_edge_store<kClsEdge1>)) return kClsEdge1;
+    if (func == reinterpret_cast<const void*>(&kb_edge_store<kClsEdge2>)) return kClsEdge2;
     if (func == reinterpret_cast<const void*>(&kb_vertex<kClsVertex0>)) return kClsVertex0;
     if (func == reinterpret_cast<const void*>(&kb_vertex<kClsVertex1>)) return kClsVertex1;
     if (func == reinterpret_cast<const void*>(&kb_vertex<kClsVertex2>)) return kClsVertex2;

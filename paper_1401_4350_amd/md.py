@@ -112,6 +112,8 @@ _SIGS = {
     "md_batch_steps_left": ([_bat_p, ctypes.c_int32, _I64P], ctypes.c_int),
     "md_batch_retire": ([_bat_p, ctypes.c_int32], ctypes.c_int),
     "md_batch_sync": ([_bat_p], ctypes.c_int),
+    "md_batch_thermostat": ([_bat_p, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
     "md_batch_info": ([_bat_p, ctypes.POINTER(MDBatchInfo)], ctypes.c_int),
     "md_batch_destroy": ([_bat_p], None),
     "md_batch_last_error": ([_bat_p], ctypes.c_char_p),
@@ -411,6 +413,12 @@ class Batch:
 
     def sync(self):
         self._check(_lib.md_batch_sync(self._h), "md_batch_sync")
+
+    def thermostat(self, slot: int, temperature: float, prob: float, seed: int, counter: int):
+        """md_batch_thermostat: the momentum refresh of an admitted system,
+        before the next batch step."""
+        self._check(_lib.md_batch_thermostat(self._h, slot, temperature, prob, seed, counter),
+                    "md_batch_thermostat")
 
     def info(self) -> dict:
         i = MDBatchInfo()

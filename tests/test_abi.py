@@ -125,7 +125,7 @@ def test_batch_params_checked_on_host(md):
     assert md.batch_workspace_bytes(ok) > 0
     n = ctypes.c_uint64()
     h = ctypes.c_void_p()
-    for field, value in [("max_systems", 0), ("mode", 3), ("steps_per_launch", 0),
+    for field, value in [("max_systems", 0), ("mode", 2), ("mode", 7), ("steps_per_launch", 0),
                          ("steps_per_launch", 5000), ("use_graph", 2), ("max_particles", 1),
                          ("pool_bytes", 0)]:
         p = md.batch_params(8, 100000, 1 << 30)

@@ -43,11 +43,11 @@ MIX = [
 ]
 
 
-def fresh(md, k, seed=11):
+def fresh(md, k, seed=11, edge_store=False):
     name, over, prec, steps = MIX[k]
     w = WORKLOADS[name].with_(**over)
     s = accepted_state(w, seed + k)
-    g = md.System(md.make_params(w, prec))
+    g = md.System(md.make_params(w, prec, edge_store=edge_store))
     g.set_state(s.x, s.v, s.q, s.angmom)
     g.build()
     return g, steps
@@ -85,7 +85,7 @@ def check_against_oracle(k, got, gstats):
 
 
 def alone(md, k, mode):
-    g, steps = fresh(md, k)
+    g, steps = fresh(md, k, edge_store=mode == "edge_det")
     g.forces(mode)
     g.step(steps, mode)
     return g.get_state(), g.stats()
@@ -98,8 +98,9 @@ def run_mix(md, mode, steps_per_launch, use_graph=True, late=(2, 5)):
     b = md.Batch(bp)
     pending = [k for k in range(len(MIX)) if k not in late]
     slots = {}
+    store = mode == "edge_det"
     for k in pending:
-        g, steps = fresh(md, k)
+        g, steps = fresh(md, k, edge_store=store)
         slots[b.admit(g, steps)] = k
     out = {}
     launches = 0
@@ -108,7 +109,7 @@ def run_mix(md, mode, steps_per_launch, use_graph=True, late=(2, 5)):
         launches += 1
         if late:
             for k in late:
-                g, steps = fresh(md, k)
+                g, steps = fresh(md, k, edge_store=store)
                 slots[b.admit(g, steps)] = k
             late = ()
         for slot in [s for s in slots if b.steps_left(s) == 0]:
@@ -155,6 +156,78 @@ def test_batch_edge_alone_and_in_mix(md):
         assert np.abs(got["v"] - ref["v"]).max() < tol, k
         if MIX[k][2] == "fp64":
             check_against_oracle(k, got, mix[k][1])
+
+
+def test_batch_edge_det_bitwise_alone_and_in_mix(md):
+    """The deterministic edge mode in the batch: per-edge records and the
+    ordered gather make every system's trajectory bitwise the one it has
+    alone; a system made without edge_store is refused."""
+    say("[batch edge_det]")
+    mix, _ = run_mix(md, "edge_det", 16)
+    for k in range(len(MIX)):
+        ref, rstats = alone(md, k, "edge_det")
+        got, gstats = mix[k]
+        for key in ref:
+            assert np.array_equal(got[key], ref[key]), (k, key)
+        assert gstats["rebuilds"] == rstats["rebuilds"]
+        if MIX[k][2] == "fp64":
+            check_against_oracle(k, got, gstats)
+    b = md.Batch(md.batch_params(2, 10000, 1 << 30, "edge_det", 8, True))
+    g, steps = fresh(md, 0)  # no edge_store
+    with pytest.raises(md.MDError) as e:
+        b.admit(g, steps)
+    assert e.value.status == -1
+    g.close()
+    b.close()
+
+
+def test_batch_thermostat_bitwise_alone(md):
+    """md_batch_thermostat between batch launches gives bitwise the state of
+    the same system stepped alone with md_thermostat at the same points (same
+    draws: the refresh is keyed by particle id, seed and counter)."""
+    say("[batch thermostat]")
+    systems = [("lj_small", {"n": 3000, "rho": 0.8}, 48), ("patchy_paper", {"n": 1200, "rho": 0.3}, 48),
+               ("lj_small", {"n": 900, "rho": 0.85}, 48)]
+    K, T, prob = 8, 0.9, 0.3
+
+    def make(k):
+        name, over, steps = systems[k]
+        w = WORKLOADS[name].with_(**over)
+        s = accepted_state(w, 70 + k)
+        g = md.System(md.make_params(w))
+        g.set_state(s.x, s.v, s.q, s.angmom)
+        g.build()
+        g.forces("vertex")
+        return g, w
+
+    thermo = (0, 1)  # systems that get the thermostat
+    b = md.Batch(md.batch_params(4, 20000, 1 << 30, "vertex", K, True))
+    slots = {}
+    for k in range(len(systems)):
+        g, _ = make(k)
+        slots[k] = b.admit(g, systems[k][2])
+    launch = 0
+    while any(b.steps_left(sl) > 0 for sl in slots.values()):
+        assert b.step() == K
+        for k in thermo:
+            b.thermostat(slots[k], T, prob, 5 + k, launch)
+        launch += 1
+    got = {k: b.retire(sl).get_state() for k, sl in slots.items()}
+    b.close()
+    for k in range(len(systems)):
+        g, w = make(k)
+        for c in range(systems[k][2] // K):
+            g.step(K, "vertex")
+            if k in thermo:
+                g.thermostat(T, prob, 5 + k, c)
+        ref = g.get_state()
+        g.close()
+        for key in ref:
+            assert np.array_equal(got[k][key], ref[key]), (k, key)
+    b2 = md.Batch(md.batch_params(2, 5000, 1 << 28, "vertex", K, True))
+    with pytest.raises(md.MDError):
+        b2.thermostat(0, T, prob, 1, 0)  # free slot
+    b2.close()
 
 
 def test_batch_cancel_and_slot_reuse(md):

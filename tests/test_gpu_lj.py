@@ -194,6 +194,34 @@ def test_trajectory_with_rebuilds(md):
         assert st["rebuilds"] == len(ref["rebuild_steps"])
 
 
+@pytest.mark.parametrize("n,dt,steps", [(3000, 0.005, 90), (4096, 0.001, 60), (700, 0.006, 37)])
+def test_fused_steps_equal_single_steps(md, n, dt, steps):
+    """md_step(k) of the vertex LJ mode runs its fused launches in batches and
+    enqueues a list rebuild when a launch reports one due (launches after it
+    do nothing until the host resumes); k calls of md_step(1) run the
+    per-step sequence (rebuild test chain, then forces).  The same arithmetic
+    and the same rebuild steps give bitwise the same state -- at time steps
+    that rebuild every few steps, so batches stop and resume many times."""
+    w = WORKLOADS["lj_small"].with_(n=n, dt=dt)
+    s = accepted_state(w, 8)
+    say(f"[fused batches] lj n={n} dt={dt} {steps} steps")
+    a = gpu_system(md, w, s)
+    a.step(steps, "vertex")
+    b = gpu_system(md, w, s)
+    for _ in range(steps):
+        b.step(1, "vertex")
+    sa, sb = a.get_state(), b.get_state()
+    ta, tb = a.stats(), b.stats()
+    a.close()
+    b.close()
+    say(f"  list builds {ta['rebuilds']} / {tb['rebuilds']}")
+    assert ta["rebuilds"] == tb["rebuilds"]
+    if dt > 0.004:
+        assert ta["rebuilds"] >= 5
+    for key in ("x", "v", "f"):
+        assert np.array_equal(sa[key], sb[key]), key
+
+
 def test_overflow_is_reported(md):
     w = WORKLOADS["lj_small"].with_(max_neighbors=16)
     s = accepted_state(w, 7)
