@@ -221,8 +221,9 @@ Layout layout(const md_params& p) {
     L.hcount = take(cur, 4 * n);
     L.hstart = take(cur, 4 * (n + 1));
     L.hj = take(cur, 4 * (uint64_t)L.max_half);
-    // packed words, four spare (the edge pass reads them four at a time)
-    L.hr = take(cur, p.pot == MD_POT_LJ ? 4 * ((uint64_t)L.max_half + 4) : 0);
+    // packed words of the edge passes (row in the tile, region index of the
+    // partner), four spare (the LJ pass reads them four at a time)
+    L.hr = take(cur, 4 * ((uint64_t)L.max_half + 4));
     // Newton mode replicas: m force arrays (and for patchy m torque arrays)
     L.rep = take(cur, (p.pot == MD_POT_LJ ? 32 : 64) * n * (uint64_t)p.newton_m);
     L.chunk_row = take(cur, 4 * ((uint64_t)L.max_half / md::kWave + 2));
@@ -472,7 +473,6 @@ void fill_sys(const md_params* p, const Layout& L, void* d_state, void* d_worksp
     long long waves = (L.max_half + md::kWave - 1) / md::kWave;
     long long blocks = (waves + 3) / 4;
     *edge_grid = (int)std::max(1LL, std::min(blocks, 4096LL));
-    y.eblk = std::min(*edge_grid, 4 * L.ntiles);  // edge blocks when stepped in a batch
     y.prec = p->prec;
 }
 

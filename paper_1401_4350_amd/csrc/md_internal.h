@@ -121,7 +121,7 @@ struct Sys {
     int* hcount;
     int* hstart;     // n + 1
     int* hj;         // half-list partner slots, CSR by row
-    unsigned* hr;    // LJ, staged tiles: per half-list entry, row in the tile << 16 | region index
+    unsigned* hr;    // tiles with a region: per half-list entry, row in the tile << 16 | region index
     double4* rep;    // Newton mode: nrep replicated force arrays of n records
     int nrep;
     int* chunk_row;  // first row of every 64-pair chunk of the half list
@@ -148,7 +148,6 @@ struct Sys {
     Ctrl* ctrl;
     int cell_order;  // md_cell_order; nonzero: no tile staged in LDS
     const int* cell_rank;  // curve orders: cell id of row-major cell (z * nc + y) * nc + x
-    int eblk;        // blocks of the edge pass (grid-stride over the half list)
     int prec;        // md_precision of the pair maths
     int launch_id;   // fused vertex steps: id of this launch (see Ctrl::req)
     int* host_run;   // fused vertex steps: host-mapped word, gets the id of every launch that runs
@@ -177,7 +176,7 @@ enum BatchClass {
     kClsVertex0,       // vertex pass: LJ ntiles; patchy ntiles or nblk (patchy_vertex_tpp)
     kClsVertex1,
     kClsVertex2,
-    kClsEdge0,         // edge pass: LJ ntiles, patchy eblk
+    kClsEdge0,         // edge pass: one block per tile
     kClsEdge1,
     kClsEdge2,
     kNumClasses
@@ -225,7 +224,7 @@ __host__ __device__ inline int class_blocks(const Sys& s, int cls) {
                        ? (s.pot == 0 || patchy_vertex_tpp(s) > 1 ? s.ntiles : s.nblk)
                        : 0;
         default:
-            return lds_bucket(s) == cls - kClsEdge0 ? (s.pot == 0 ? s.ntiles : s.eblk) : 0;
+            return lds_bucket(s) == cls - kClsEdge0 ? s.ntiles : 0;
     }
 }
 

@@ -612,7 +612,7 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane) {
 __device__ __forceinline__ void b_tile_region(const Sys& s, int t) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nc = s.nc;
-    if (nc < 3 || s.pot != 0 || s.cell_order != 0) {  // gathers from global memory
+    if (nc < 3 || s.cell_order != 0) {  // gathers from global memory
         if (lane == 0) s.tile_nseg[t] = -1;
         return;
     }
@@ -699,6 +699,11 @@ __device__ __forceinline__ int tile_lds_base(const int4* seg, int nseg, int cb, 
     }
     return -1;
 }
+
+// Packed half-list word of the patchy edge pass: partner not in the region.
+constexpr int kNoRegion = 0xffff;
+// Image code (two bits per axis, shift + 1) of a slot seen without a shift.
+constexpr int kCodeHome = 1 | 1 << 2 | 1 << 4;
 
 // ---------------------------------------------------------------------------
 // Copy of a staged tile's region into LDS (list build and vertex pass).
@@ -854,7 +859,9 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     const bool act = i < s.n;
     const int ii = act ? i : s.n - 1;
     const bool tact = tile < s.ntiles;
-    const int nseg = tact ? s.tile_nseg[tile] : -1;
+    // LJ lists of a tile with a region hold region indices; patchy lists
+    // always hold slots (their regions serve the edge pass's accumulator)
+    const int nseg = tact && s.pot == 0 ? s.tile_nseg[tile] : -1;
     const double4 xi = s.tpos[ii];
     if (act) {
         s.pos[i] = xi;
@@ -1141,7 +1148,11 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
     const int lane = threadIdx.x & (kWave - 1);
     const int gshift = lane & ~(TPP - 1);
     const bool act = i < s.n;
-    const int nseg = s.tile_nseg[tile];
+    const int nseg = s.pot == 0 ? s.tile_nseg[tile] : -1;  // region-index lists (LJ)
+    // four-patch particles: the tile's region, for the region indices of the
+    // partners that the edge pass accumulates over
+    const int rseg = s.pot != 0 && s.p64.model == 0 ? s.tile_nseg[tile] : -1;
+    __shared__ int4 sg[kSegMax];
     if (nseg >= 0) {
         const int nchk = s.tile_nchunk[tile];
         const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
@@ -1149,6 +1160,8 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
             int4 d = chk[c];
             if (lane < d.y - d.x) map[d.z + lane] = (d.x + lane) | d.w << kSlotBits;
         }
+    } else if (rseg >= 0 && (int)threadIdx.x < rseg) {
+        sg[threadIdx.x] = s.tile_seg[(size_t)tile * kSegMax + threadIdx.x];
     }
     if (threadIdx.x < kTile) {
         int ip = tile * kTile + threadIdx.x;
@@ -1204,8 +1217,14 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
         if (keep && kk < end) {
             s.hj[kk] = ent;
             // the edge pass accumulates by region index and finds the row in
-            // the high half
-            if (nseg >= 0) s.hr[kk] = (unsigned)reg | (unsigned)(i - tile * kTile) << 16;
+            // the high half (four patches: the region index of slot j in the
+            // image of the entry, kNoRegion outside the region)
+            if (nseg >= 0) {
+                s.hr[kk] = (unsigned)reg | (unsigned)(i - tile * kTile) << 16;
+            } else if (rseg >= 0) {
+                const int rg = tile_lds_base(sg, rseg, j, (unsigned)ent >> kSlotBits);
+                s.hr[kk] = (unsigned)(rg >= 0 ? rg : kNoRegion) | (unsigned)(i - tile * kTile) << 16;
+            }
         }
         k += __builtin_popcount(grp);
     }
@@ -1230,7 +1249,7 @@ __device__ __forceinline__ void b_col_fill(const Sys& s, int bid, int nb) {
     const int q = threadIdx.x % TPP;
     const int lane = threadIdx.x & (kWave - 1);
     const bool act = i < s.n;
-    const int nseg = s.tile_nseg[tile];
+    const int nseg = s.pot == 0 ? s.tile_nseg[tile] : -1;  // region-index lists
     if (nseg >= 0) {
         const int nchk = s.tile_nchunk[tile];
         const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
@@ -2267,6 +2286,170 @@ __global__ __launch_bounds__(kBlock) void k_edge_lj_tile(Sys s) {
     b_edge_lj_tile<PREC, STAGE>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
+// Patchy edge pass by tiles (the four-patch model), one workgroup per tile of
+// kTile rows, one lane per half-list entry (positions and orientations
+// gathered from global memory).
+// Each pair is evaluated once and zero results are skipped.  ACC, for a tile
+// with a region: the partner's force and torque go into an LDS accumulator
+// over the region (six planes), the row's share (combined over the lanes of
+// the row by a segmented shuffle reduction) goes into the same accumulator at
+// the row's own region index, so a particle that is both a row and a partner
+// of the tile, or the partner of several rows, costs one global atomic per
+// component at the end, when every non-zero accumulator is flushed (the
+// region in runs of consecutive slots).  Other tiles add the partner's share
+// with global atomics and the rows' shares through per-row LDS sums.  Forces
+// and torques must be zero on entry.
+// The two-patch model keeps the pass by 64-entry chunks (k_edge): its chains
+// give about one bonded partner per particle, so partners are hardly ever
+// shared inside a tile and the tile's set-up and flush cost more than the
+// global atomics they save (measured: the tile pass was 19 % slower there,
+// and 2-21 % faster for four patches).
+__device__ __host__ __forceinline__ bool patchy_edge_by_tile(const Sys& s) { return s.p64.model == 0; }
+constexpr int kPatchyAccCapMax = 2240;  // largest region accumulated in LDS
+__host__ __device__ constexpr bool patchy_edge_accumulates(int cap) { return cap <= kPatchyAccCapMax; }
+__host__ __device__ __forceinline__ size_t patchy_edge_lds_bytes(int cap) {
+    return patchy_edge_accumulates(cap) ? 6 * sizeof(double) * (size_t)lds_plane(cap) : 0;
+}
+
+template <int PREC, bool ACC>
+__device__ __forceinline__ void b_edge_patchy_tile(const Sys& s, int tile) {
+    using R = typename std::conditional<PREC == 0, double, float>::type;
+    extern __shared__ double acc[];
+    __shared__ double fi[6 * kTile];  // per-row sums of tiles without a region
+    __shared__ int hs[kTile + 1];     // the rows' half-list starts
+    __shared__ int rreg[kTile];       // the rows' own region indices
+    __shared__ int4 sg[kSegMax];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t0 = tile * kTile;
+    const int nrow = min(kTile, s.n - t0);
+    const int nseg = ACC ? s.tile_nseg[tile] : -1;
+    const bool reg = nseg >= 0;
+    const int plane = lds_plane(s.lds_cap);
+    if (reg) {
+        for (int k = threadIdx.x; k < 6 * plane; k += kBlock) acc[k] = 0.0;
+        if (threadIdx.x < nseg) sg[threadIdx.x] = s.tile_seg[(size_t)tile * kSegMax + threadIdx.x];
+    }
+    for (int k = threadIdx.x; k < 6 * kTile; k += kBlock) fi[k] = 0.0;
+    if (threadIdx.x <= nrow) hs[threadIdx.x] = s.hstart[t0 + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x < kTile)
+        rreg[threadIdx.x] = reg && (int)threadIdx.x < nrow
+                                ? tile_lds_base(sg, nseg, t0 + (int)threadIdx.x, kCodeHome)
+                                : -1;
+    __syncthreads();
+    const int e0 = hs[0], e1 = hs[nrow];
+    double* F = reinterpret_cast<double*>(s.frc);
+    double* T = reinterpret_cast<double*>(s.trq);
+    for (int base = e0; base < e1; base += kBlock) {
+        const int e = base + threadIdx.x;
+        const bool valid = e < e1;
+        const int es = min(e, e1 - 1);
+        int lo = 0, hi = nrow;  // hs[lo] <= es < hs[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (hs[mid] <= es) lo = mid;
+            else hi = mid;
+        }
+        const int i = t0 + lo;
+        const int ent = s.hj[es];
+        const int j = min(entry_slot(ent), s.n - 1);
+        const double4 xi = s.pos[i], xj = s.pos[j];
+        const double dx = xj.x - xi.x + image(ent, 0, s.box);
+        const double dy = xj.y - xi.y + image(ent, 1, s.box);
+        const double dz = xj.z - xi.z + image(ent, 2, s.box);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        V3<double> fj = {0, 0, 0}, ti = {0, 0, 0}, tj = {0, 0, 0};
+        if (valid && r2 < s.rc2) {
+            V3<double> ui[4], uj[4];
+            patch_dirs<double>(s.quat[i], ui, s.p64.model);
+            patch_dirs<double>(s.quat[j], uj, s.p64.model);
+            const V3<double> d = {dx, dy, dz};
+            double v;
+            patchy_pair<R>(d, r2, ui, uj, s, fj, ti, tj, v);
+        }
+        const bool fnz = (fj.x != 0.0) | (fj.y != 0.0) | (fj.z != 0.0);
+        const bool tjnz = (tj.x != 0.0) | (tj.y != 0.0) | (tj.z != 0.0);
+        const bool tinz = (ti.x != 0.0) | (ti.y != 0.0) | (ti.z != 0.0);
+        // partner share: only non-zero results touch memory
+        const int r = reg ? (int)(s.hr[es] & 0xffff) : kNoRegion;
+        if (r != kNoRegion) {
+            if (fnz) {
+                unsafeAtomicAdd(&acc[r], fj.x);
+                unsafeAtomicAdd(&acc[plane + r], fj.y);
+                unsafeAtomicAdd(&acc[2 * plane + r], fj.z);
+            }
+            if (tjnz) {
+                unsafeAtomicAdd(&acc[3 * plane + r], tj.x);
+                unsafeAtomicAdd(&acc[4 * plane + r], tj.y);
+                unsafeAtomicAdd(&acc[5 * plane + r], tj.z);
+            }
+        } else {
+            if (fnz) {
+                unsafeAtomicAdd(F + 4 * (size_t)j + 0, fj.x);
+                unsafeAtomicAdd(F + 4 * (size_t)j + 1, fj.y);
+                unsafeAtomicAdd(F + 4 * (size_t)j + 2, fj.z);
+            }
+            if (tjnz) {
+                unsafeAtomicAdd(T + 4 * (size_t)j + 0, tj.x);
+                unsafeAtomicAdd(T + 4 * (size_t)j + 1, tj.y);
+                unsafeAtomicAdd(T + 4 * (size_t)j + 2, tj.z);
+            }
+        }
+        // row share: the lanes of each row combined, one lane adds the sums
+        if (__any(fnz | tinz)) {
+            const int key = valid ? lo : kTile + lane;
+            const double sx = seg_sum(-fj.x, key, lane);
+            const double sy = seg_sum(-fj.y, key, lane);
+            const double sz = seg_sum(-fj.z, key, lane);
+            const double ux = seg_sum(ti.x, key, lane);
+            const double uy = seg_sum(ti.y, key, lane);
+            const double uz = seg_sum(ti.z, key, lane);
+            const int up = __shfl_up(key, 1);
+            const bool head = valid && (lane == 0 || up != key);
+            if (head) {
+                const int rr = rreg[lo];
+                double* a = rr >= 0 ? acc + rr : fi + 6 * lo;
+                const int st = rr >= 0 ? plane : 1;
+                if ((sx != 0.0) | (sy != 0.0) | (sz != 0.0)) {
+                    unsafeAtomicAdd(a, sx);
+                    unsafeAtomicAdd(a + st, sy);
+                    unsafeAtomicAdd(a + 2 * st, sz);
+                }
+                if ((ux != 0.0) | (uy != 0.0) | (uz != 0.0)) {
+                    unsafeAtomicAdd(a + 3 * st, ux);
+                    unsafeAtomicAdd(a + 4 * st, uy);
+                    unsafeAtomicAdd(a + 5 * st, uz);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (reg) {
+        region_acc_flush(s, acc, plane, tile, F);
+        region_acc_flush(s, acc + 3 * plane, plane, tile, T);
+    }
+    if (threadIdx.x < nrow) {
+        const double* a = fi + 6 * threadIdx.x;
+        double* g = F + 4 * (size_t)(t0 + threadIdx.x);
+        double* h = T + 4 * (size_t)(t0 + threadIdx.x);
+        if ((a[0] != 0.0) | (a[1] != 0.0) | (a[2] != 0.0)) {
+            unsafeAtomicAdd(g + 0, a[0]);
+            unsafeAtomicAdd(g + 1, a[1]);
+            unsafeAtomicAdd(g + 2, a[2]);
+        }
+        if ((a[3] != 0.0) | (a[4] != 0.0) | (a[5] != 0.0)) {
+            unsafeAtomicAdd(h + 0, a[3]);
+            unsafeAtomicAdd(h + 1, a[4]);
+            unsafeAtomicAdd(h + 2, a[5]);
+        }
+    }
+}
+
+template <int PREC, bool ACC>
+__global__ __launch_bounds__(kBlock) void k_edge_patchy_tile(Sys s) {
+    b_edge_patchy_tile<PREC, ACC>(s, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // ---------------------------------------------------------------------------
 // Vertex decomposition with Newton's third law (LJ).  The TPP lanes of
 // particle i walk its half list (partners j > i), evaluate each pair once,
@@ -2763,8 +2946,13 @@ static void edge_dispatch(const Sys& s, int grid, hipStream_t st) {
             hipLaunchKernelGGL((k_edge_lj_tile<PREC, true>), dim3((unsigned)s.ntiles), b, sh, st, s);
         else
             hipLaunchKernelGGL((k_edge_lj_tile<PREC, false>), dim3((unsigned)s.ntiles), b, sh, st, s);
-    } else {
+    } else if (!patchy_edge_by_tile(s)) {
         hipLaunchKernelGGL((k_edge<1, PREC>), g, b, 0, st, s);
+    } else if (patchy_edge_accumulates(s.lds_cap)) {
+        hipLaunchKernelGGL((k_edge_patchy_tile<PREC, true>), dim3((unsigned)s.ntiles), b,
+                           patchy_edge_lds_bytes(s.lds_cap), st, s);
+    } else {
+        hipLaunchKernelGGL((k_edge_patchy_tile<PREC, false>), dim3((unsigned)s.ntiles), b, 0, st, s);
     }
 }
 
@@ -3164,9 +3352,13 @@ __global__ __launch_bounds__(kBlock) void kb_edge(BatchDev b, int step) {
             constexpr bool stage = edge_stages_positions(bucket_cap(C - kClsEdge0));
             if (s.prec == 0) b_edge_lj_tile<0, stage>(s, lb, s.ntiles);
             else b_edge_lj_tile<1, stage>(s, lb, s.ntiles);
+        } else if (patchy_edge_by_tile(s)) {
+            constexpr bool acc = patchy_edge_accumulates(bucket_cap(C - kClsEdge0));
+            if (s.prec == 0) b_edge_patchy_tile<0, acc>(s, lb);
+            else b_edge_patchy_tile<1, acc>(s, lb);
         } else {
-            if (s.prec == 0) b_edge<1, 0>(s, lb, s.eblk);
-            else b_edge<1, 1>(s, lb, s.eblk);
+            if (s.prec == 0) b_edge<1, 0>(s, lb, s.ntiles);
+            else b_edge<1, 1>(s, lb, s.ntiles);
         }
     });
 }
@@ -3224,9 +3416,11 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
             hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
             per_bucket([&](auto bk) {
                 constexpr int B = decltype(bk)::value;
+                // the larger of the LJ and patchy passes' LDS
+                constexpr int cap = bucket_cap(B);
+                const size_t sh = std::max(edge_lds_bytes(cap), patchy_edge_lds_bytes(cap));
                 if (grid[kClsEdge0 + B] > 0)
-                    hipLaunchKernelGGL(kb_edge<kClsEdge0 + B>, g(kClsEdge0 + B), blk,
-                                       edge_lds_bytes(bucket_cap(B)), st, b, k);
+                    hipLaunchKernelGGL(kb_edge<kClsEdge0 + B>, g(kClsEdge0 + B), blk, sh, st, b, k);
             });
             hipLaunchKernelGGL(kb_kick, g(kClsParticle), blk, 0, st, b, k);
         }

@@ -84,6 +84,27 @@ def test_patchy_forces_torques_fp64(md, case, mode):
     np.testing.assert_allclose(ep, e, rtol=0, atol=1e-12 * max(np.abs(e).max(), 1e-300))
 
 
+def test_patchy_edge_region_accumulation(md):
+    """The four-patch edge pass sums a tile's partner and row shares in LDS
+    over the tile's region (slot and image of each partner looked up at the
+    half-list fill); tiles without a region add with global atomics.  Here a
+    tile covers about 13 of a row's 16 cells, so most tiles span two rows of
+    cells; the result is held to the FP64 bars."""
+    w = WORKLOADS["patchy"].with_(n=20000, rho=0.7)
+    s = accepted_state(w, 4)
+    g = gpu_system(md, w, s)
+    st = g.stats()
+    say(f"[patchy edge regions] tiles with a region {st['tiles_staged']}/{st['tiles_total']}")
+    assert 0 < st["tiles_staged"] <= st["tiles_total"]
+    g.forces("edge")
+    out = g.get_state()
+    g.close()
+    F, T, _, _, _, _ = oracle.patchy_forces(s.x, s.q, s.box, patchy_params(w), with_abs=True)
+    FP, TP = oracle.patchy_pair_scales(s.x, s.q, s.box, patchy_params(w))
+    assert cond_rel_err(out["f"], F, FP) <= 1e-10
+    assert cond_rel_err(out["torque"], T, TP) <= 1e-10
+
+
 @pytest.mark.parametrize("mode", ["vertex", "edge"])
 def test_patchy_forces_fp32(md, mode):
     w = WORKLOADS["patchy"].with_(n=3000)
