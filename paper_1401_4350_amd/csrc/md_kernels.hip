@@ -919,103 +919,132 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
         count++;
     };
     if (nseg >= 0) {
-        // Staged tile: the wavefront walks the tile's region segment by
-        // segment, in list order (home row, dz, dy, then the two slots of a
-        // row that wraps the box), every lane testing the same candidate, so
-        // the records come through scalar loads.  A segment covers the home
-        // cells' x-range plus one cell either side, so it holds each lane's
-        // three cells of that row; cells further out are beyond r_v.
+        // Staged tile: every lane walks its own 27 cells, row of cells by row
+        // (dz, dy) in list order, each row as one run of consecutive slots
+        // (cells cx - 1 .. cx + 1), or two where the row wraps the box; the
+        // lanes of one home cell read the same records, so a wavefront's
+        // load touches a few distinct addresses.  A run lies inside one
+        // segment of the tile's region (the segment of the lane's home row
+        // for that (dz, dy) and image), which gives the entries' region
+        // indices.  The test runs in FP32 on the rounded copy of the records,
+        // as t = |x_j - x_i|^2 - lo: t < 0 is in; t >= w (lo + w is the
+        // band's top) is out; a candidate with t in [0, w) is decided in
+        // FP64, so the list is the one the FP64 test gives.
         const int hr = cz * nc + cy - s.tile_row0[tile];  // the lane's home row in the tile
-        const auto* sg = as_const(s.tile_seg + (size_t)tile * kSegMax);
-        const auto* cp = as_const(s.tposf);
-        const auto* cp64 = as_const(s.tpos);
+        const bool inr = act && (unsigned)hr <= 1u;
+        const int4* sgp = s.tile_seg + (size_t)tile * kSegMax + (inr ? hr : 0) * 18;
         const float nlo = -s.rv2_lo;
         const unsigned wbits = __float_as_uint(s.rv2_band);
-        for (int h = 0; h < 2; h++) {
-            const bool inh = act && hr == h;
-            if (!__any(inh)) continue;
-            for (int q = 0; q < 18; q++) {
-                const ci4 g = sg[h * 18 + q];
-                if (g.x >= g.y) continue;
-                // x_i in the segment's periodic image
-                const double sx = xi.x - (double)((g.w & 3) - 1) * s.box;
-                const double sy = xi.y - (double)(((g.w >> 2) & 3) - 1) * s.box;
-                const double sz = xi.z - (double)(((g.w >> 4) & 3) - 1) * s.box;
-                const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
-                const int roff = g.z - g.x;  // region index of slot j: roff + j
-                // The test runs in FP32 on the rounded copy of the records,
-                // as t = |x_j - x_i|^2 - lo: t < 0 is in; t >= w (lo + w is
-                // the band's top) is out; a candidate with t in [0, w) is
-                // decided in FP64, so the list is the one the FP64 test gives.
-                auto tbits = [&](const cf4& pf) {
-                    const float ex = pf.x - fx, ey = pf.y - fy, ez = pf.z - fz;
-                    return __float_as_uint(
-                        __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, __builtin_fmaf(ex, ex, nlo))));
-                };
-                // Hits collect as bits j - c0 of (ma, mb) and are appended
-                // per part of at most 128 candidates.
-                auto flush = [&](int c0, int c1, unsigned long long ma, unsigned long long mb) {
-                    const int nv = c1 - c0;
-                    if (nv < 64) ma &= (1ull << nv) - 1;
-                    mb &= nv >= 128 ? ~0ull : (nv > 64 ? (1ull << (nv - 64)) - 1 : 0ull);
-                    const int bi = i - c0;  // the particle itself
-                    if ((unsigned)bi < 64u) ma &= ~(1ull << bi);
-                    else if ((unsigned)(bi - 64) < 64u) mb &= ~(1ull << (bi - 64));
-                    if (!inh) ma = mb = 0;
-                    while (ma | mb) {
-                        const bool low = ma != 0;
-                        const unsigned long long x = low ? ma : mb;
-                        const int j = c0 + __builtin_ctzll(x) + (low ? 0 : 64);
-                        const unsigned long long x2 = x & (x - 1);
-                        ma = low ? x2 : ma;
-                        mb = low ? mb : x2;
-                        append16(j, roff + j);
+        auto wrapc = [&](int v) { return v < 0 ? 0 : (v >= nc ? 2 : 1); };  // shift -L, 0, +L
+        // first cell of the lane's run 0 and the last (run 1 exists only for
+        // cx = 0 and cx = nc - 1, where the row wraps the box)
+        const int xa0 = cx == 0 ? nc - 1 : cx - 1;
+        const int xb0 = cx == 0 ? nc - 1 : (cx == nc - 1 ? nc - 1 : cx + 1);
+        const int nrun = __any(inr && (cx == 0 || cx == nc - 1)) ? 2 : 1;
+        auto row_of = [&](int r) {  // row of cells (dz, dy) = (r / 3 - 1, r % 3 - 1)
+            int az = cz + r / 3 - 1, ay = cy + r % 3 - 1;
+            az += az < 0 ? nc : (az >= nc ? -nc : 0);
+            ay += ay < 0 ? nc : (ay >= nc ? -nc : 0);
+            return (az * nc + ay) * nc;
+        };
+        // run 0 bounds of the next row, loaded one row ahead
+        int ncb = inr ? s.cstart[row_of(0) + xa0] : 0;
+        int nce = inr ? s.cstart[row_of(0) + xb0 + 1] : 0;
+        for (int r = 0; r < 9; r++) {
+            const int dz = r / 3 - 1, dy = r % 3 - 1;
+            {
+                const int zc = wrapc(cz + dz), yc = wrapc(cy + dy);
+                const int rowbase = row_of(r);
+                const int cb0 = ncb, ce0 = nce;
+                if (r < 8) {
+                    ncb = inr ? s.cstart[row_of(r + 1) + xa0] : 0;
+                    nce = inr ? s.cstart[row_of(r + 1) + xb0 + 1] : 0;
+                }
+                const int4 g0 = sgp[r * 2];
+                const int4 g1 = sgp[r * 2 + 1];
+                for (int run = 0; run < nrun; run++) {
+                    // the run's cells [xa, xb] and x image code
+                    int xa, xb, xc;
+                    if (cx == 0) {
+                        xa = run ? 0 : nc - 1, xb = run ? 1 : nc - 1, xc = run ? 1 : 0;
+                    } else if (cx == nc - 1) {
+                        xa = run ? 0 : nc - 2, xb = run ? 0 : nc - 1, xc = run ? 2 : 1;
+                    } else {
+                        xa = cx - 1, xb = run ? cx - 2 : cx + 1, xc = 1;  // one run
                     }
-                };
-                // Eight candidates per round (reads past the segment's end
-                // land in the copy or its spare records; their bits are
-                // cleared); the next round's records are loaded before this
-                // round is tested.
-                cf4 qn[8];
+                    const bool has = inr && xb >= xa;
+                    const int cb = run == 0 ? cb0 : (has ? s.cstart[rowbase + xa] : 0);
+                    const int ce = run == 0 ? ce0 : (has ? s.cstart[rowbase + xb + 1] : 0);
+                    const int code = xc | yc << 2 | zc << 4;
+                    const bool m0 = g0.w == code && cb >= g0.x && cb < g0.y;
+                    const bool m1 = g1.w == code && cb >= g1.x && cb < g1.y;
+                    const int roff = m0 ? g0.z - g0.x : g1.z - g1.x;  // region index of j: roff + j
+                    const int end = (m0 || m1) ? ce : cb;
+                    if (ce > cb && !(m0 || m1)) atomicOr(&s.ctrl->overflow, 2);  // region misses the run
+                    // x_i in the run's periodic image
+                    const double sx = xi.x - (double)(xc - 1) * s.box;
+                    const double sy = xi.y - (double)(yc - 1) * s.box;
+                    const double sz = xi.z - (double)(zc - 1) * s.box;
+                    const float fx = (float)sx, fy = (float)sy, fz = (float)sz;
+                    auto tbits = [&](const float4& pf) {
+                        const float ex = pf.x - fx, ey = pf.y - fy, ez = pf.z - fz;
+                        return __float_as_uint(
+                            __builtin_fmaf(ez, ez, __builtin_fmaf(ey, ey, __builtin_fmaf(ex, ex, nlo))));
+                    };
+                    // hits collect as bits j - c0 of ma and are appended per
+                    // window of 64 candidates (the particle itself and slots
+                    // past the run's end are never set)
+                    auto flush = [&](int c0, unsigned long long ma) {
+                        while (ma) {
+                            const int j = c0 + __builtin_ctzll(ma);
+                            ma &= ma - 1;
+                            append16(j, roff + j);
+                        }
+                    };
+                    // eight candidates per round (reads past the run's end
+                    // land in the copy or its spare records); the next
+                    // round's records are loaded before this round is tested
+                    float4 qn[8];
 #pragma unroll
-                for (int u = 0; u < 8; u++) qn[u] = cp[g.x + u];
-                unsigned long long ma = 0, mb = 0;
-                int c0 = g.x;
-                for (int j0 = g.x; j0 < g.y; j0 += 8) {
-                    cf4 pv[8];
+                    for (int u = 0; u < 8; u++) qn[u] = s.tposf[cb + u];
+                    unsigned long long ma = 0;
+                    int c0 = cb;
+                    for (int j0 = cb; j0 < end; j0 += 8) {
+                        float4 pv[8];
 #pragma unroll
-                    for (int u = 0; u < 8; u++) pv[u] = qn[u];
+                        for (int u = 0; u < 8; u++) pv[u] = qn[u];
 #pragma unroll
-                    for (int u = 0; u < 8; u++) qn[u] = cp[j0 + 8 + u];
-                    unsigned m8 = 0, tmin = ~0u;
-#pragma unroll
-                    for (int u = 0; u < 8; u++) {
-                        const unsigned tb = tbits(pv[u]);
-                        tmin = min(tmin, tb);
-                        m8 |= (tb >> 31) << u;
-                    }
-                    if (tmin < wbits) {  // rare: FP64 decides the candidates in the band
+                        for (int u = 0; u < 8; u++) qn[u] = s.tposf[j0 + 8 + u];
+                        unsigned m8 = 0, tmin = ~0u;
 #pragma unroll
                         for (int u = 0; u < 8; u++) {
-                            const int j = j0 + u;
-                            if (tbits(pv[u]) < wbits && j < g.y) {
-                                const cd4 pj = cp64[j];
-                                const double dx = pj.x - sx, dy = pj.y - sy, dz = pj.z - sz;
-                                if (dx * dx + dy * dy + dz * dz < rv2) m8 |= 1u << u;
+                            const unsigned tb = tbits(pv[u]);
+                            tmin = min(tmin, tb);
+                            m8 |= (tb >> 31) << u;
+                        }
+                        if (tmin < wbits) {  // rare: FP64 decides the candidates in the band
+#pragma unroll
+                            for (int u = 0; u < 8; u++) {
+                                const int j = j0 + u;
+                                if (tbits(pv[u]) < wbits && j < end) {
+                                    const double4 pj = s.tpos[j];
+                                    const double dx = pj.x - sx, dy = pj.y - sy, dz = pj.z - sz;
+                                    if (dx * dx + dy * dy + dz * dz < rv2) m8 |= 1u << u;
+                                }
                             }
                         }
+                        const int left = end - j0;
+                        if (left < 8) m8 &= (1u << left) - 1;
+                        if ((unsigned)(i - j0) < 8u) m8 &= ~(1u << (i - j0));
+                        ma |= (unsigned long long)m8 << (j0 - c0);
+                        if (j0 - c0 == 56) {  // a window of 64 is full
+                            flush(c0, ma);
+                            ma = 0;
+                            c0 = j0 + 8;
+                        }
                     }
-                    const int o = j0 - c0;
-                    const unsigned long long w = (unsigned long long)m8 << (o & 63);
-                    ma |= o < 64 ? w : 0ull;
-                    mb |= o < 64 ? 0ull : w;
-                    if (o + 8 == 128 && j0 + 8 < g.y) {  // a part of 128 is full
-                        flush(c0, c0 + 128, ma, mb);
-                        ma = mb = 0;
-                        c0 = j0 + 8;
-                    }
+                    flush(c0, ma);
                 }
-                flush(c0, g.y, ma, mb);
             }
         }
         if (act && (unsigned)hr > 1u) atomicOr(&s.ctrl->overflow, 2);  // region misses the particle

@@ -50,12 +50,17 @@ def stats_markdown(trace_csv: str, command: str, top: int = 40,
         agg.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     rows = sorted(agg.items(), key=lambda kv: -sum(kv[1]))
     out = [f"Command: `{command}`", "",
-           "| kernel | workgroups | calls | total ms | average us | min us | max us |",
-           "|---|---:|---:|---:|---:|---:|---:|"]
+           "Full launches: the calls that took at least half the longest one (launches that "
+           "return at once -- a rebuild step with no rebuild due, a fused step launch whose "
+           "lists are stale -- are the others).", "",
+           "| kernel | workgroups | calls | total ms | average us | min us | max us "
+           "| full calls | full average us |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
     rows = rows[:top] + [r for r in rows[top:] if any(s in r[0][0] for s in keep)]
     for (name, wg), d in rows:
+        full = [x for x in d if x >= 0.5 * max(d)]
         out.append(f"| `{name[:70]}` | {wg} | {len(d)} | {sum(d) / 1e3:.3f} | {sum(d) / len(d):.2f} "
-                   f"| {min(d):.2f} | {max(d):.2f} |")
+                   f"| {min(d):.2f} | {max(d):.2f} | {len(full)} | {sum(full) / len(full):.2f} |")
     return "\n".join(out) + "\n"
 
 
@@ -77,6 +82,9 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int) -> dic
         vals = [v for k, vs in agg.items() if kernel in k for v in vs]
         if not vals:
             raise SystemExit(f"no dispatch of {kernel} in {d}")
+        # full launches only (a fused step launch that finds its lists stale
+        # returns at once and moves almost nothing)
+        vals = [v for v in vals if v >= 0.5 * max(vals)]
         mean_kib = sum(vals) / len(vals)
         out[f"{key}_kib_per_dispatch"] = mean_kib
         out[f"{key}_copy_kib"] = copy_kib
