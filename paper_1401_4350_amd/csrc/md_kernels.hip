@@ -884,7 +884,8 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
     const double rv2 = s.rv2;
     int count = 0, half = 0;
     int e0 = 0, e1 = 0, e2 = 0;  // entries of the current row not yet written
-    int w0 = 0, w1 = 0, w2 = 0, w3 = 0;  // staged tile: the current row of eight 16-bit entries
+    // staged tile: entry k of the lane's particle is 16-bit word list_off16(k)
+    uint16_t* wrow16 = reinterpret_cast<uint16_t*>(list_row_w(s, tact ? i : ii));
     // Appends entry `ent` for partner j; a row of four goes out in one store.
     auto append = [&](int j, int ent) {
         if (count < cap) {
@@ -900,20 +901,12 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
         }
         count++;
     };
-    // Staged tile: appends region index `reg` for partner j (16-bit entries).
+    // Staged tile: appends region index `reg` for partner j (16-bit entries,
+    // stored one by one: the hits of a lane come in a divergent loop, where a
+    // store costs less than keeping a row of eight in registers).
     auto append16 = [&](int j, int reg) {
         if (count < cap) {
-            const int sl = count & 7, wd = sl >> 1;
-            const bool hi = sl & 1;
-            const int v = hi ? reg << 16 : reg;
-            w0 = wd == 0 ? (hi ? w0 | v : v) : w0;
-            w1 = wd == 1 ? (hi ? w1 | v : v) : w1;
-            w2 = wd == 2 ? (hi ? w2 | v : v) : w2;
-            w3 = wd == 3 ? (hi ? w3 | v : v) : w3;
-            if (sl == 7) {
-                *wrow = make_int4(w0, w1, w2, w3);
-                wrow += kTile;
-            }
+            wrow16[list_off16(count)] = (uint16_t)reg;
             half += j > i;
         }
         count++;
@@ -1121,22 +1114,9 @@ __device__ __forceinline__ void b_build(const Sys& s, int bid, int nb) {
         // reads whole rows without masking what lies past a list's end.
         // (A particle's rows hold 8 * mcap >= 16 entries, mcap >= 2.)
         const int bound = min((min(mx, cap) + 15) & ~15, 8 * s.mcap);
-        const int pad = s.lds_cap;
-        if (tact) {  // also the rows of slots past n, which the vertex pass reads
-            for (int c = min(count, cap); c < bound; c++) {
-                const int sl = c & 7, wd = sl >> 1;
-                const bool hi = sl & 1;
-                const int v = hi ? pad << 16 : pad;
-                w0 = wd == 0 ? (hi ? w0 | v : v) : w0;
-                w1 = wd == 1 ? (hi ? w1 | v : v) : w1;
-                w2 = wd == 2 ? (hi ? w2 | v : v) : w2;
-                w3 = wd == 3 ? (hi ? w3 | v : v) : w3;
-                if (sl == 7) {
-                    *wrow = make_int4(w0, w1, w2, w3);
-                    wrow += kTile;
-                }
-            }
-        }
+        const uint16_t pad = (uint16_t)s.lds_cap;
+        if (tact)  // also the rows of slots past n, which the vertex pass reads
+            for (int c = min(count, cap); c < bound; c++) wrow16[list_off16(c)] = pad;
     } else if (act && (min(count, cap) & 3)) {  // last, partial row
         *wrow = make_int4(e0, e1, e2, 0);
     }
