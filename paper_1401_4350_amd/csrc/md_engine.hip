@@ -32,9 +32,9 @@ struct Layout {
     uint64_t pos, vel, frc, quat, angm, trq, id;
     // workspace offsets
     uint64_t pos_alt, xbuild, tpos, tposf, tvel, tquat, tangm, tid, cell, rank, ccount, cstart, order, nbr,
-        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, tmax, sync, ef, eidx, cell_rank, epart, wpart, kpart, red, ctrl, tile_seg,
+        ncount, hcount, hstart, hj, hr, rep, chunk_row, bsum, tmax, sync, ef, eidx, cell_rank, epart, wpart, kpart, fpl, red, ctrl, tile_seg,
         tile_nseg, tile_chunk, tile_nchunk, tile_row0;
-    int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0;
+    int nc = 0, ncell = 0, nblk = 0, ntiles = 0, lds_cap = 0, fps = 0;
     long long max_half = 0;
 };
 
@@ -244,6 +244,10 @@ Layout layout(const md_params& p) {
     L.epart = take(cur, 8 * n);
     L.wpart = take(cur, 8 * n);
     L.kpart = take(cur, 8 * n);
+    // LJ edge pass: force planes (x, y, z of every slot in arrays of their
+    // own), each plane padded to a multiple of 32 doubles
+    L.fps = (int)((n + 31) / 32 * 32);
+    L.fpl = take(cur, p.pot == MD_POT_LJ ? 24 * (uint64_t)L.fps : 0);
     L.red = take(cur, 8 * (3 * (uint64_t)md::kRedBlocks + 3));
     L.ws_bytes = cur;
     return L;
@@ -468,6 +472,8 @@ void fill_sys(const md_params* p, const Layout& L, void* d_state, void* d_worksp
     y.epart = (double*)(W + L.epart);
     y.wpart = (double*)(W + L.wpart);
     y.kpart = (double*)(W + L.kpart);
+    y.fpl = (double*)(W + L.fpl);
+    y.fps = L.fps;
     y.red = (double*)(W + L.red);
 
     long long waves = (L.max_half + md::kWave - 1) / md::kWave;

@@ -143,6 +143,8 @@ struct Sys {
     int* tile_row0;  // first home row (z * nc + y) of the tile
     double* epart;   // per-particle potential energy
     double* wpart;   // per-particle virial
+    double* fpl;     // LJ edge pass: force planes, component c of slot k at fpl[c * fps + k]
+    int fps;         // plane stride (doubles)
     double* kpart;   // per-particle kinetic energy
     double* red;     // reduction partials (3 * kRedBlocks) + result (3)
     Ctrl* ctrl;

@@ -730,7 +730,7 @@ __host__ __device__ __forceinline__ size_t lds_acc_bytes(int cap) {
 }
 
 struct RegionBatch {
-    static constexpr int R = 8;
+    static constexpr int R = 10;  // one batch covers most regions (40 chunks, 2 560 slots)
     double4 p[R];
     int4 d[R];
 };
@@ -1516,6 +1516,11 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     int ii = act ? i : s.n - 1;  // idle lanes stay for the group shuffle
     double4 xi = s.pos[ii];
     int cnt = act ? s.ncount[ii] : 0;
+    // the kick's and drift's own loads, issued now so that the epilogue does
+    // not wait for memory
+    double4 vi = make_double4(0, 0, 0, 0), xb = make_double4(0, 0, 0, 0);
+    if (KICK && act && q == 0) vi = s.vel[i];
+    if (DRIFT && act && q == 0) xb = s.xbuild[i];
     Acc3<PREC> f;
     double e = 0, w = 0;
     if (nseg >= 0) {
@@ -1543,25 +1548,24 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
         // The list build pads a staged tile's lists with the padding slot up
         // to the tile's longest list rounded up to 16 entries, which covers
         // every group of four lane entries below mmax: no masking here.
-        auto load_block = [&](int n0, int (&en)[E]) {
+        // The words stay packed (two entries each) until they are used.
+        auto load_block = [&](int n0, unsigned (&wd)[E / 2]) {
             const int* bp = lane_rows + (size_t)(n0 >> 1) * (kTile * 4);
 #pragma unroll
-            for (int m = 0; m < E / 2; m++) {
-                const int v = __builtin_nontemporal_load(bp + m * (kTile * 4));
-                en[2 * m] = v & 0xffff;
-                en[2 * m + 1] = (int)((unsigned)v >> 16);
-            }
+            for (int m = 0; m < E / 2; m++)
+                wd[m] = (unsigned)__builtin_nontemporal_load(bp + m * (kTile * 4));
         };
         // groups of four: the four records are read from LDS before the
         // first is used, so their latencies overlap
-        auto eval_block = [&](int m0, const int (&en)[E]) {
+        auto eval_block = [&](int m0, const unsigned (&wd)[E / 2]) {
 #pragma unroll
             for (int m = 0; m < E; m += 4) {
                 if (m0 + m < mmax) {
                     double px[4], py[4], pz[4];
 #pragma unroll
                     for (int u = 0; u < 4; u++) {
-                        const unsigned a = 3u * (unsigned)en[m + u];
+                        const unsigned w = wd[(m + u) >> 1];
+                        const unsigned a = 3u * ((m + u) & 1 ? w >> 16 : w & 0xffffu);
                         px[u] = lds3[a];
                         py[u] = lds3[a + 1];
                         pz[u] = lds3[a + 2];
@@ -1571,7 +1575,7 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
                 }
             }
         };
-        int ea[E], eb[E];
+        unsigned ea[E / 2], eb[E / 2];
         load_block(0, ea);
         region_store(s, lds3, rb);
         region_finish(s, s.pos, lds3, cap, tile, nchk, wv, rb);
@@ -1611,7 +1615,7 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
     if (!DRIFT) s.frc[i] = make_double4(fx, fy, fz, 0.0);
     if (!isfinite(fx + fy + fz)) atomicOr(&s.ctrl->nonfinite, 1);
     if (KICK) {
-        double4 v = s.vel[i];
+        double4 v = vi;
         v.x += s.hdt * fx * s.inv_mass;
         v.y += s.hdt * fy * s.inv_mass;
         v.z += s.hdt * fz * s.inv_mass;
@@ -1624,7 +1628,6 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
             x.y += s.dt * v.y;
             x.z += s.dt * v.z;
             s.pos_alt[i] = x;
-            const double4 xb = s.xbuild[i];
             const double ddx = x.x - xb.x, ddy = x.y - xb.y, ddz = x.z - xb.z;
             if (ddx * ddx + ddy * ddy + ddz * ddz > s.disp2) {
                 s.ctrl->rebuild = 1;
@@ -2017,10 +2020,13 @@ template <int POT>
 __global__ __launch_bounds__(kBlock) void k_edge_gather(Sys s) { b_edge_gather<POT>(s, blockIdx.x, gridDim.x); }
 
 // Adds a staged tile's region accumulator (three planes, like the staged
-// positions) to the global forces: one atomic per non-zero component, the
+// positions) to global memory: one atomic per non-zero component, the
 // region's slots in runs of consecutive slots (one wavefront per run).
+// Component c of slot k is dst[c * cstride + k * sstride]: the records of F
+// (cstride 1, sstride 4) or the force planes (cstride s.fps, sstride 1).
 __device__ __forceinline__ void region_acc_flush(const Sys& s, const double* acc, int plane,
-                                                 int tile, double* F) {
+                                                 int tile, double* dst, size_t cstride = 1,
+                                                 int sstride = 4) {
     const int lane = threadIdx.x & (kWave - 1);
     const int nchk = s.tile_nchunk[tile];
     const int4* chk = s.tile_chunk + (size_t)tile * kChunkMax;
@@ -2030,10 +2036,10 @@ __device__ __forceinline__ void region_acc_flush(const Sys& s, const double* acc
             const int r = d.z + lane;
             const double vx = acc[r], vy = acc[plane + r], vz = acc[2 * plane + r];
             if ((vx != 0.0) | (vy != 0.0) | (vz != 0.0)) {
-                double* g = F + 4 * (size_t)(d.x + lane);
-                unsafeAtomicAdd(g + 0, vx);
-                unsafeAtomicAdd(g + 1, vy);
-                unsafeAtomicAdd(g + 2, vz);
+                double* g = dst + (size_t)sstride * (size_t)(d.x + lane);
+                unsafeAtomicAdd(g, vx);
+                unsafeAtomicAdd(g + cstride, vy);
+                unsafeAtomicAdd(g + 2 * cstride, vz);
             }
         }
     }
@@ -2052,12 +2058,14 @@ __device__ __forceinline__ void region_acc_flush(const Sys& s, const double* acc
 // row and added to a per-row LDS accumulator once per run.  At the end every
 // non-zero accumulator is added to global memory with one atomic per
 // component (the region in runs of consecutive slots).  Zero results are
-// skipped throughout.
+// skipped throughout.  The pass adds into the force planes (x, y and z in
+// arrays of their own, so the atomics of a run of slots are 8 bytes apart);
+// the closing kick, or k_forces_from_planes, gives the force records.
 //
 // Other tiles (b_edge_lj_gather): one entry per lane, positions gathered from
 // global memory, the row found by binary search over the tile's row starts,
 // the partner's share added with global atomics, the row's share combined by
-// a segmented shuffle reduction.  Forces must be zero on entry.
+// a segmented shuffle reduction.  The force planes must be zero on entry.
 
 // Dynamic LDS of the LJ edge pass: with staged positions the region copy and
 // its accumulator, else the accumulator alone (regions too large for both
@@ -2066,6 +2074,21 @@ constexpr int kEdgeStageCapMax = 3072;
 __host__ __device__ constexpr bool edge_stages_positions(int cap) { return cap <= kEdgeStageCapMax; }
 __host__ __device__ __forceinline__ size_t edge_lds_bytes(int cap) {
     return (edge_stages_positions(cap) ? lds_region_bytes(cap) : 0) + lds_acc_bytes(cap);
+}
+
+// Adds the per-row sums of an LJ edge tile (three doubles per row) to the
+// force planes, one atomic per non-zero component.
+__device__ __forceinline__ void edge_rows_flush(const Sys& s, const double* fi, int t0, int nrow) {
+    if (threadIdx.x < nrow) {
+        const double vx = fi[3 * threadIdx.x], vy = fi[3 * threadIdx.x + 1],
+                     vz = fi[3 * threadIdx.x + 2];
+        if ((vx != 0.0) | (vy != 0.0) | (vz != 0.0)) {
+            double* g = s.fpl + (size_t)(t0 + threadIdx.x);
+            unsafeAtomicAdd(g, vx);
+            unsafeAtomicAdd(g + s.fps, vy);
+            unsafeAtomicAdd(g + 2 * (size_t)s.fps, vz);
+        }
+    }
 }
 
 template <int PREC>
@@ -2086,7 +2109,8 @@ __device__ __forceinline__ void b_edge_lj_gather(const Sys& s, int tile, double*
     if (threadIdx.x <= nrow) hs[threadIdx.x] = s.hstart[t0 + threadIdx.x];
     __syncthreads();
     const int e0 = hs[0], e1 = hs[nrow];
-    double* F = reinterpret_cast<double*>(s.frc);
+    double* const P = s.fpl;  // force planes: component c of slot k at P[c * fps + k]
+    const size_t fps = (size_t)s.fps;
     for (int base = e0; base < e1; base += kBlock) {
         const int e = base + threadIdx.x;
         const bool valid = e < e1;
@@ -2127,9 +2151,9 @@ __device__ __forceinline__ void b_edge_lj_gather(const Sys& s, int tile, double*
                 unsafeAtomicAdd(&acc[plane + r], fy);
                 unsafeAtomicAdd(&acc[2 * plane + r], fz);
             } else {
-                unsafeAtomicAdd(F + 4 * (size_t)j + 0, fx);
-                unsafeAtomicAdd(F + 4 * (size_t)j + 1, fy);
-                unsafeAtomicAdd(F + 4 * (size_t)j + 2, fz);
+                unsafeAtomicAdd(P + j, fx);
+                unsafeAtomicAdd(P + fps + j, fy);
+                unsafeAtomicAdd(P + 2 * fps + j, fz);
             }
         }
         if (__any(nz)) {
@@ -2147,17 +2171,8 @@ __device__ __forceinline__ void b_edge_lj_gather(const Sys& s, int tile, double*
         }
     }
     __syncthreads();
-    if (staged) region_acc_flush(s, acc, plane, tile, F);
-    if (threadIdx.x < nrow) {
-        const double vx = fi[3 * threadIdx.x], vy = fi[3 * threadIdx.x + 1],
-                     vz = fi[3 * threadIdx.x + 2];
-        if ((vx != 0.0) | (vy != 0.0) | (vz != 0.0)) {
-            double* g = F + 4 * (size_t)(t0 + threadIdx.x);
-            unsafeAtomicAdd(g + 0, vx);
-            unsafeAtomicAdd(g + 1, vy);
-            unsafeAtomicAdd(g + 2, vz);
-        }
-    }
+    if (staged) region_acc_flush(s, acc, plane, tile, P, fps, 1);
+    edge_rows_flush(s, fi, t0, nrow);
 }
 
 
@@ -2265,18 +2280,8 @@ __device__ __forceinline__ void b_edge_lj_staged(const Sys& s, int tile, double*
         w = wn;
     }
     __syncthreads();
-    double* F = reinterpret_cast<double*>(s.frc);
-    region_acc_flush(s, acc, plane, tile, F);
-    if (threadIdx.x < nrow) {
-        const double vx = fi[3 * threadIdx.x], vy = fi[3 * threadIdx.x + 1],
-                     vz = fi[3 * threadIdx.x + 2];
-        if ((vx != 0.0) | (vy != 0.0) | (vz != 0.0)) {
-            double* g = F + 4 * (size_t)(t0 + threadIdx.x);
-            unsafeAtomicAdd(g + 0, vx);
-            unsafeAtomicAdd(g + 1, vy);
-            unsafeAtomicAdd(g + 2, vz);
-        }
-    }
+    region_acc_flush(s, acc, plane, tile, s.fpl, (size_t)s.fps, 1);
+    edge_rows_flush(s, fi, t0, nrow);
 }
 
 // STAGE: the launch's dynamic LDS holds the region copy as well
@@ -2752,7 +2757,14 @@ __device__ __forceinline__ void b_kick_drift(const Sys& s, int bid, int nb) {
         }
         if (ZERO) s.trq[i] = make_double4(0, 0, 0, 0);
     }
-    if (ZERO) s.frc[i] = make_double4(0, 0, 0, 0);
+    if (ZERO) {
+        s.frc[i] = make_double4(0, 0, 0, 0);
+        if (POT == 0) {  // the LJ edge pass adds into the force planes
+            s.fpl[i] = 0.0;
+            s.fpl[s.fps + i] = 0.0;
+            s.fpl[2 * (size_t)s.fps + i] = 0.0;
+        }
+    }
     double4 xb = s.xbuild[i];
     double ddx = x.x - xb.x;
     double ddy = x.y - xb.y;
@@ -2763,12 +2775,20 @@ __device__ __forceinline__ void b_kick_drift(const Sys& s, int bid, int nb) {
 template <int POT, bool ZERO>
 __global__ __launch_bounds__(kBlock) void k_kick_drift(Sys s) { b_kick_drift<POT, ZERO>(s, blockIdx.x, gridDim.x); }
 
-template <int POT>
+// PLANES (LJ edge pass): the forces come from the force planes and are
+// stored into the force records on the way.
+template <int POT, bool PLANES = false>
 __device__ __forceinline__ void b_kick(const Sys& s, int bid, int nb) {
     int i = bid * kBlock + threadIdx.x;
     if (bid == 0 && threadIdx.x == 0) s.ctrl->rebuild = 0;
     if (i >= s.n) return;
-    double4 f = s.frc[i];
+    double4 f;
+    if (PLANES) {
+        f = make_double4(s.fpl[i], s.fpl[s.fps + i], s.fpl[2 * (size_t)s.fps + i], 0.0);
+        s.frc[i] = f;
+    } else {
+        f = s.frc[i];
+    }
     double4 v = s.vel[i];
     v.x += s.hdt * f.x * s.inv_mass;
     v.y += s.hdt * f.y * s.inv_mass;
@@ -2787,14 +2807,29 @@ __device__ __forceinline__ void b_kick(const Sys& s, int bid, int nb) {
     if (!isfinite(chk)) atomicOr(&s.ctrl->nonfinite, 1);
 }
 
-template <int POT>
-__global__ __launch_bounds__(kBlock) void k_kick(Sys s) { b_kick<POT>(s, blockIdx.x, gridDim.x); }
+template <int POT, bool PLANES = false>
+__global__ __launch_bounds__(kBlock) void k_kick(Sys s) { b_kick<POT, PLANES>(s, blockIdx.x, gridDim.x); }
 
 __global__ __launch_bounds__(kBlock) void k_zero_forces(Sys s) {
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= s.n) return;
     s.frc[i] = make_double4(0, 0, 0, 0);
-    if (s.pot == 1) s.trq[i] = make_double4(0, 0, 0, 0);
+    if (s.pot == 1) {
+        s.trq[i] = make_double4(0, 0, 0, 0);
+    } else {
+        s.fpl[i] = 0.0;
+        s.fpl[s.fps + i] = 0.0;
+        s.fpl[2 * (size_t)s.fps + i] = 0.0;
+    }
+}
+
+// Force records from the force planes (LJ edge pass without a kick).
+__global__ __launch_bounds__(kBlock) void k_forces_from_planes(Sys s) {
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    const double fx = s.fpl[i], fy = s.fpl[s.fps + i], fz = s.fpl[2 * (size_t)s.fps + i];
+    s.frc[i] = make_double4(fx, fy, fz, 0.0);
+    if (!isfinite(fx + fy + fz)) atomicOr(&s.ctrl->nonfinite, 1);
 }
 
 // Clears the rebuild flag after a stand-alone edge pass (the vertex kernel
@@ -3030,8 +3065,15 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
         if (!kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) edge_dispatch<0>(s, edge_grid, st);
         else edge_dispatch<1>(s, edge_grid, st);  // FP32 pair maths, FP64 atomics
-        if (kick) closing_kick(false);
-        else hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
+        if (kick && s.pot == 0) {  // LJ: the forces are in the planes
+            if (mid) (void)hipEventRecord(mid, st);
+            hipLaunchKernelGGL((k_kick<0, true>), grid_n(s.n), dim3(kBlock), 0, st, s);
+        } else if (kick) {
+            closing_kick(false);
+        } else {
+            if (s.pot == 0) hipLaunchKernelGGL(k_forces_from_planes, grid_n(s.n), dim3(kBlock), 0, st, s);
+            hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
+        }
     }
     return hipGetLastError();
 }
@@ -3372,9 +3414,11 @@ __global__ __launch_bounds__(kBlock) void kb_edge(BatchDev b, int step) {
     });
 }
 
+// PLANES: after the atomic edge pass, whose LJ forces are in the planes.
+template <bool PLANES>
 __global__ __launch_bounds__(kBlock) void kb_kick(BatchDev b, int step) {
     batch_block<kClsParticle>(b, step, [](const Sys& s, int lb) {
-        if (s.pot == 0) b_kick<0>(s, lb, s.nblk);
+        if (s.pot == 0) b_kick<0, PLANES>(s, lb, s.nblk);
         else b_kick<1>(s, lb, s.nblk);
     });
 }
@@ -3420,7 +3464,7 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
                     hipLaunchKernelGGL(kb_edge_store<kClsEdge0 + B>, g(kClsEdge0 + B), blk, 0, st, b, k);
             });
             hipLaunchKernelGGL(kb_edge_gather, g(kClsTile), blk, 0, st, b, k);
-            hipLaunchKernelGGL(kb_kick, g(kClsParticle), blk, 0, st, b, k);
+            hipLaunchKernelGGL(kb_kick<false>, g(kClsParticle), blk, 0, st, b, k);
         } else {
             hipLaunchKernelGGL(kb_half_fill, g(kClsTile), blk, sh_map, st, b, k);
             per_bucket([&](auto bk) {
@@ -3431,7 +3475,7 @@ hipError_t launch_batch_steps(const BatchDev& b, const int* grid, int mode, int 
                 if (grid[kClsEdge0 + B] > 0)
                     hipLaunchKernelGGL(kb_edge<kClsEdge0 + B>, g(kClsEdge0 + B), blk, sh, st, b, k);
             });
-            hipLaunchKernelGGL(kb_kick, g(kClsParticle), blk, 0, st, b, k);
+            hipLaunchKernelGGL(kb_kick<true>, g(kClsParticle), blk, 0, st, b, k);
         }
     }
     hipLaunchKernelGGL(kb_advance, dim3((b.nslots + kBlock - 1) / kBlock), blk, 0, st, b, steps);
@@ -3444,7 +3488,8 @@ int batch_kernel_class(const void* func) {
                               reinterpret_cast<const void*>(&kb_cell_bin),
                               reinterpret_cast<const void*>(&kb_cell_scatter),
                               reinterpret_cast<const void*>(&kb_build),
-                              reinterpret_cast<const void*>(&kb_kick)};
+                              reinterpret_cast<const void*>(&kb_kick<false>),
+                              reinterpret_cast<const void*>(&kb_kick<true>)};
     for (const void* f : particle)
         if (f == func) return kClsParticle;
     if (func == reinterpret_cast<const void*>(&kb_sort_tiles)) return kClsSortTiles;
