@@ -422,7 +422,7 @@ const char* md_batch_last_error(const md_batch* b);
  * MD_ERR_BUFFER_TOO_SMALL if the system needs more than
  * MD_STATIC_SCRATCH_BYTES: it needs state_bytes + workspace_bytes of
  * md_query_sizes (an LJ fluid at rho = 0.8 with max_neighbors 208 about
- * 1.8 kB per particle, so up to about 35 000 particles).  MD_ERR_HIP if a
+ * 2.0 kB per particle, so up to about 33 000 particles).  MD_ERR_HIP if a
  * launch fails.
  *
  * Every call on one GPU uses that GPU's one array, which keeps the last

@@ -702,6 +702,18 @@ __device__ __forceinline__ int tile_lds_base(const int4* seg, int nseg, int cb, 
 
 // Packed half-list word of the patchy edge pass: partner not in the region.
 constexpr int kNoRegion = 0xffff;
+// The patchy edge pass goes by tiles (k_edge_patchy_tile) for the four-patch
+// model from 256 tiles (16 384 particles) on; otherwise by 64-entry chunks
+// (k_edge).  The two-patch chains give about one bonded partner per particle,
+// so partners are hardly ever shared inside a tile and the tile's set-up and
+// flush cost more than the global atomics they save (the tile pass measured
+// 19 % slower there); small systems leave most of the chip idle, where the
+// tile's serial set-up and flush show (33 against 25 us at 4 096 particles),
+// while from 16 384 particles on the tile pass is 2-21 % faster.
+constexpr int kPatchyTileMin = 256;
+__device__ __host__ __forceinline__ bool patchy_edge_by_tile(const Sys& s) {
+    return s.p64.model == 0 && s.ntiles >= kPatchyTileMin;
+}
 // Image code (two bits per axis, shift + 1) of a slot seen without a shift.
 constexpr int kCodeHome = 1 | 1 << 2 | 1 << 4;
 
@@ -1158,9 +1170,9 @@ __device__ __forceinline__ void b_half_fill(const Sys& s, int bid, int nb) {
     const int gshift = lane & ~(TPP - 1);
     const bool act = i < s.n;
     const int nseg = s.pot == 0 ? s.tile_nseg[tile] : -1;  // region-index lists (LJ)
-    // four-patch particles: the tile's region, for the region indices of the
-    // partners that the edge pass accumulates over
-    const int rseg = s.pot != 0 && s.p64.model == 0 ? s.tile_nseg[tile] : -1;
+    // patchy particles whose edge pass goes by tiles: the tile's region, for
+    // the region indices of the partners it accumulates over
+    const int rseg = s.pot != 0 && patchy_edge_by_tile(s) ? s.tile_nseg[tile] : -1;
     __shared__ int4 sg[kSegMax];
     if (nseg >= 0) {
         const int nchk = s.tile_nchunk[tile];
@@ -2300,7 +2312,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_lj_tile(Sys s) {
     b_edge_lj_tile<PREC, STAGE>(s, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
-// Patchy edge pass by tiles (the four-patch model), one workgroup per tile of
+// Patchy edge pass by tiles (patchy_edge_by_tile), one workgroup per tile of
 // kTile rows, one lane per half-list entry (positions and orientations
 // gathered from global memory).
 // Each pair is evaluated once and zero results are skipped.  ACC, for a tile
@@ -2313,12 +2325,6 @@ __global__ __launch_bounds__(kBlock) void k_edge_lj_tile(Sys s) {
 // region in runs of consecutive slots).  Other tiles add the partner's share
 // with global atomics and the rows' shares through per-row LDS sums.  Forces
 // and torques must be zero on entry.
-// The two-patch model keeps the pass by 64-entry chunks (k_edge): its chains
-// give about one bonded partner per particle, so partners are hardly ever
-// shared inside a tile and the tile's set-up and flush cost more than the
-// global atomics they save (measured: the tile pass was 19 % slower there,
-// and 2-21 % faster for four patches).
-__device__ __host__ __forceinline__ bool patchy_edge_by_tile(const Sys& s) { return s.p64.model == 0; }
 constexpr int kPatchyAccCapMax = 2240;  // largest region accumulated in LDS
 __host__ __device__ constexpr bool patchy_edge_accumulates(int cap) { return cap <= kPatchyAccCapMax; }
 __host__ __device__ __forceinline__ size_t patchy_edge_lds_bytes(int cap) {
@@ -2472,9 +2478,9 @@ __global__ __launch_bounds__(kBlock) void k_edge_patchy_tile(Sys s) {
 // arrays (chosen per wavefront), i's own sum is stored straight into F (its
 // only writer), and a combining pass adds the replicas to F and clears them.
 // !REP: the partner share of a staged tile goes into an LDS accumulator over
-// the tile's region, added to F once per workgroup (region_acc_flush); i's
-// own sum and unstaged partners are added to F atomically, so F must be zero
-// on entry.
+// the tile's region, added once per workgroup (region_acc_flush); i's own sum
+// and unstaged partners are added atomically.  These adds go to the force
+// planes (as in the edge pass), which must be zero on entry.
 // ---------------------------------------------------------------------------
 template <int PREC, bool REP>
 __device__ __forceinline__ void b_newton_lj(const Sys& s, int tile, int nb) {
@@ -2495,8 +2501,7 @@ __device__ __forceinline__ void b_newton_lj(const Sys& s, int tile, int nb) {
     const int e0 = act ? s.hstart[ii] : 0;
     const int e1 = act ? s.hstart[ii + 1] : 0;
     const double4 xi = s.pos[ii];
-    double* F = reinterpret_cast<double*>(s.frc);
-    double* Rp = F;
+    double* Rp = nullptr;
     if (REP) {
         const long long wave = (long long)tile * (kBlock / kWave) + threadIdx.x / kWave;
         Rp = reinterpret_cast<double*>(s.rep + (size_t)(wave % s.nrep) * s.n);
@@ -2532,11 +2537,15 @@ __device__ __forceinline__ void b_newton_lj(const Sys& s, int tile, int nb) {
                     unsafeAtomicAdd(&acc[r], gx);
                     unsafeAtomicAdd(&acc[plane + r], gy);
                     unsafeAtomicAdd(&acc[2 * plane + r], gz);
-                } else {
+                } else if (REP) {
                     double* g = Rp + 4 * (size_t)j;
                     unsafeAtomicAdd(g + 0, gx);
                     unsafeAtomicAdd(g + 1, gy);
                     unsafeAtomicAdd(g + 2, gz);
+                } else {
+                    unsafeAtomicAdd(s.fpl + j, gx);
+                    unsafeAtomicAdd(s.fpl + s.fps + j, gy);
+                    unsafeAtomicAdd(s.fpl + 2 * (size_t)s.fps + j, gz);
                 }
             }
         }
@@ -2551,14 +2560,14 @@ __device__ __forceinline__ void b_newton_lj(const Sys& s, int tile, int nb) {
         if (REP) {
             s.frc[i] = make_double4(fx, fy, fz, 0.0);
         } else if ((fx != 0.0) | (fy != 0.0) | (fz != 0.0)) {
-            unsafeAtomicAdd(F + 4 * (size_t)i + 0, fx);
-            unsafeAtomicAdd(F + 4 * (size_t)i + 1, fy);
-            unsafeAtomicAdd(F + 4 * (size_t)i + 2, fz);
+            unsafeAtomicAdd(s.fpl + i, fx);
+            unsafeAtomicAdd(s.fpl + s.fps + i, fy);
+            unsafeAtomicAdd(s.fpl + 2 * (size_t)s.fps + i, fz);
         }
     }
     if (!REP) {
         __syncthreads();
-        if (staged) region_acc_flush(s, acc, plane, tile, F);
+        if (staged) region_acc_flush(s, acc, plane, tile, s.fpl, (size_t)s.fps, 1);
     }
 }
 
@@ -3042,8 +3051,17 @@ hipError_t launch_forces(const Sys& s, int mode, int prec, bool kick, hipStream_
         if (s.nrep == 0 && !kick) hipLaunchKernelGGL(k_zero_forces, grid_n(s.n), dim3(kBlock), 0, st, s);
         if (prec == 0) newton_dispatch<0>(s, st);
         else newton_dispatch<1>(s, st);  // FP32 pair maths, FP64 sums
-        if (kick) closing_kick(s.nrep > 0);
-        else if (s.nrep > 0) hipLaunchKernelGGL(k_newton_combine<false>, grid_n(s.n), dim3(kBlock), 0, st, s);
+        const bool planes = s.pot == 0 && s.nrep == 0;  // LJ with LDS accumulation
+        if (kick && planes) {
+            if (mid) (void)hipEventRecord(mid, st);
+            hipLaunchKernelGGL((k_kick<0, true>), grid_n(s.n), dim3(kBlock), 0, st, s);
+        } else if (kick) {
+            closing_kick(s.nrep > 0);
+        } else if (s.nrep > 0) {
+            hipLaunchKernelGGL(k_newton_combine<false>, grid_n(s.n), dim3(kBlock), 0, st, s);
+        } else if (planes) {
+            hipLaunchKernelGGL(k_forces_from_planes, grid_n(s.n), dim3(kBlock), 0, st, s);
+        }
         if (!kick) hipLaunchKernelGGL(k_clear_rebuild, dim3(1), dim3(1), 0, st, s.ctrl);
     } else if (mode == 3) {  // deterministic edge: per-edge results, then a gather
         if (!s.estore) return hipErrorInvalidValue;
