@@ -799,10 +799,12 @@ static md_status step_fused(md_system* s, int nsteps) {
             return s->fail(MD_ERR_STATE, "internal: fused steps make no progress");
         }
         if (ran < b.n) {
-            // a rebuild is due: every later launch did nothing
+            // a rebuild is due: every later launch does nothing, the batch
+            // still in flight included, so the rebuild chain is enqueued
+            // behind it at once (the stream keeps the order; waiting for
+            // that batch first would leave the GPU idle while the host
+            // catches up)
             if (inflight) {
-                e = hipEventSynchronize(s->fev[head]);
-                if (e != hipSuccess) return fail(e, "fused step wait");
                 issued -= q[head].n;
                 head ^= 1;
                 inflight = 0;
