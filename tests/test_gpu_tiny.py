@@ -35,8 +35,8 @@ def workload(n, box):
     return WORKLOADS["lj_small"].with_(n=n, rho=n / box ** 3)
 
 
-def tiny_state(w, seed):
-    """Seeded positions with no pair closer than 0.95 sigma and no distance
+def tiny_state(w, seed, dmin=0.95):
+    """Seeded positions with no pair closer than dmin (sigma) and no distance
     within 1e-6 of r_c or r_v; two particles sit 1.07 sigma apart across the
     periodic boundary in x.  Velocities Gaussian with the mean removed."""
     rng = np.random.default_rng(seed)
@@ -50,7 +50,7 @@ def tiny_state(w, seed):
                 c = rng.uniform(0, L, 3)
                 d = x - c
                 d -= L * np.rint(d / L)
-                if len(x) == 0 or np.min(np.sum(d * d, axis=1)) > 0.95 ** 2:
+                if len(x) == 0 or np.min(np.sum(d * d, axis=1)) > dmin ** 2:
                     x = np.vstack([x, c])
             if oracle.pair_margin(x, L, [w.rcut, w.rcut + w.skin]) > 1e-6:
                 break
@@ -107,6 +107,87 @@ def test_tiny_trajectory(md, n, box, mode):
     d -= w.box * np.rint(d / w.box)
     assert np.abs(d).max() < 1e-9
     assert np.abs(out["v"] - ref["v"]).max() < 1e-9
+    if ref["disp_margin"] > 1e-12:
+        assert g.stats()["rebuilds"] == len(ref["rebuild_steps"])
+    g.close()
+
+
+# Patchy models (four tetrahedral patches; the paper's two polar patches): the
+# same smallest sizes, boxes of two and three cells per side of each model's
+# list range, forces and torques against the oracle's per-pair scales.
+PATCHY = {"tetra": ("patchy", 0), "polar2": ("patchy_paper", 1)}
+
+
+def patchy_workload(model, n, cells):
+    base = WORKLOADS[PATCHY[model][0]]
+    box = cells * base.rv + (0.1 if cells == 2 else 0.4)
+    return base.with_(n=n, rho=n / box ** 3)
+
+
+def patchy_params(w, model):
+    return oracle.Patchy(eps=w.eps, sigma=w.sigma, rcut=w.rcut, eps_p=w.eps_p, w=w.patch_w,
+                         delta=w.patch_delta, rpc=w.patch_rcut, model=PATCHY[model][1])
+
+
+def patchy_state(w, model, seed):
+    # the two-patch core (sigma/r)^200 is kept above 1.04 sigma, as in its inputs
+    x, v = tiny_state(w, seed, dmin=1.04 if model == "polar2" else 0.95)
+    rng = np.random.default_rng(seed + 1000)
+    q = rng.normal(size=(w.n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    am = rng.normal(0.0, 0.3, (w.n, 3))
+    return x, v, q, am
+
+
+PATCHY_CASES = [(2, 2), (3, 2), (12, 2), (2, 3), (3, 3), (63, 3), (64, 3), (65, 3)]
+
+
+@pytest.mark.parametrize("model", list(PATCHY))
+@pytest.mark.parametrize("n,cells", PATCHY_CASES)
+@pytest.mark.parametrize("mode", ["vertex", "edge"])
+def test_tiny_patchy_forces_torques(md, model, n, cells, mode):
+    w = patchy_workload(model, n, cells)
+    x, v, q, am = patchy_state(w, model, 31 + n)
+    say(f"[tiny patchy] {model} n={n} cells={cells} box={w.box:.3f} {mode}")
+    g = md.System(md.make_params(w, "fp64"))
+    g.set_state(x, v, q, am)
+    g.build()
+    assert np.array_equal(g.pairs(), oracle.pairs(x, w.box, w.rv))
+    g.forces(mode)
+    out = g.get_state()
+    P = patchy_params(w, model)
+    F, T, e, wv, FA, TA = oracle.patchy_forces(x, q, w.box, P, with_abs=True)
+    FP, TP = oracle.patchy_pair_scales(x, q, w.box, P)
+    if n == 2:
+        assert np.abs(F).max() > 0  # the two cores overlap across the boundary
+    assert cond_rel_err(out["f"], F, FP) <= 1e-10
+    assert cond_rel_err(out["torque"], T, TP) <= 1e-10
+    ke, pe, vir = g.energy()
+    assert pe == pytest.approx(e.sum(), rel=0, abs=1e-12 * np.abs(e).sum() + 1e-300)
+    g.close()
+
+
+@pytest.mark.parametrize("model", list(PATCHY))
+@pytest.mark.parametrize("mode", ["vertex", "edge"])
+def test_tiny_patchy_trajectory(md, model, mode):
+    """100 rotational velocity-Verlet steps of 65 particles in a box of three
+    cells per side against the oracle's run."""
+    w = patchy_workload(model, 65, 3)
+    x, v, q, am = patchy_state(w, model, 41)
+    say(f"[tiny patchy trajectory] {model} {mode}")
+    ref = oracle.run(x, v, w.box, pot="patchy", nsteps=100, dt=w.dt, skin=w.skin,
+                     patchy=patchy_params(w, model), q=q, angmom=am, inertia=w.inertia)
+    g = md.System(md.make_params(w, "fp64"))
+    g.set_state(x, v, q, am)
+    g.build()
+    g.step(100, mode)
+    out = g.get_state()
+    d = out["x"] - ref["x"]
+    d -= w.box * np.rint(d / w.box)
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(out["v"] - ref["v"]).max() < 1e-9
+    assert np.abs(out["angmom"] - ref["angmom"]).max() < 1e-9
+    assert np.abs(np.abs((out["q"] * ref["q"]).sum(1)) - 1).max() < 1e-12
     if ref["disp_margin"] > 1e-12:
         assert g.stats()["rebuilds"] == len(ref["rebuild_steps"])
     g.close()
