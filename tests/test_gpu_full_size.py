@@ -8,7 +8,9 @@ benchmark times.
     velocities within 1e-9, the same number of list builds);
   - lj_many_dense (N = 262 144, rho = 1.0, r_c = 3.0): pair set and FP64
     vertex and edge forces (1e-10 per component against sum_j |F*_ij|);
-  - lj_precision (N = 1 048 576): the neighbour pair set.
+  - lj_precision (N = 1 048 576): the neighbour pair set;
+  - the largest size the boundary accepts (N = 2^24, LJ at rho = 0.8): FP64
+    vertex and edge forces and energies.
 
 The oracle's pair sets come from its cell enumeration, which the CPU tests
 pin equal to its O(N^2) brute force.  States are drawn until no pair distance
@@ -100,3 +102,30 @@ def test_lj_many_dense_forces(md, mode):
     err = cond_rel_err(f, F, A)
     say(f"  force error {err:.3e}")
     assert err <= 1e-10
+
+
+def test_max_size_forces(md):
+    """The largest system the boundary accepts (2^24 particles, LJ at
+    rho = 0.8, box 275.8 sigma): list build and both force passes against the
+    oracle's FP64 forces (1e-10 per component of sum_j |F*_ij|) and energies.
+    Seed 1's state has no pair distance within 3.3e-9 sigma of r_c or r_v
+    (the oracle's margin routine, run once offline: it takes minutes at this
+    size), far above the 1e-13 rounding of coordinates of this magnitude."""
+    w = WORKLOADS["lj_many"].with_(n=1 << 24)
+    from paper_1401_4350_amd.inputs import make_state
+    s = make_state(w, 1)
+    say(f"[max size] n={w.n} box={w.box:.4f}")
+    g = gpu_system(md, w, s)
+    st = g.stats()
+    say(f"  |E| {st['pairs']}; staged tiles {st['tiles_staged']}/{st['tiles_total']}")
+    F, e, wv, A = oracle.lj_forces(s.x, s.box, oracle.LJ(w.eps, w.sigma, w.rcut), with_abs=True)
+    for mode in ("vertex", "edge"):
+        say(f"  forces {mode}")
+        g.forces(mode)
+        out = g.get_state()
+        assert cond_rel_err(out["f"], F, A) <= 1e-10
+        ke, pe, vir = g.energy()
+        assert pe == pytest.approx(e.sum(), rel=0, abs=1e-12 * np.abs(e).sum())
+        assert vir == pytest.approx(wv.sum(), rel=0, abs=1e-12 * np.abs(wv).sum())
+        del out
+    g.close()
