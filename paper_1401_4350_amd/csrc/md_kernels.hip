@@ -1551,9 +1551,10 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
         // The word of lane entries n, n + 1 (n even) in row n / 2 sits at
         // int offset 256 (n / 2) + threadIdx.x of the tile's rows, so a block
         // of E entries is one lane base plus constant offsets.  Every lane
-        // issues all E / 2 loads (the list allocation has kListPadRows spare
-        // rows after the last tile), so no load sits behind a branch; entries
-        // past the lane's list end become the padding slot.
+        // issues the loads of the words below the wavefront's longest lane
+        // list (a wave-uniform test; the list allocation has kListPadRows
+        // spare rows after the last tile); entries past the lane's own list
+        // end become the padding slot.
         static_assert(TPP == 4 && kTile * TPP == kBlock, "word offset 256 m + tid");
         static_assert(E % 2 == 0 && E / 2 <= kListPadRows, "prefetch beyond the spare rows");
         const int* lane_rows = s.nbr + (size_t)tile * s.mcap * (kTile * 4) + threadIdx.x;
@@ -1564,8 +1565,10 @@ __device__ __forceinline__ void b_vertex_lj(const Sys& s, int bid, int nb) {
         auto load_block = [&](int n0, unsigned (&wd)[E / 2]) {
             const int* bp = lane_rows + (size_t)(n0 >> 1) * (kTile * 4);
 #pragma unroll
-            for (int m = 0; m < E / 2; m++)
-                wd[m] = (unsigned)__builtin_nontemporal_load(bp + m * (kTile * 4));
+            for (int m = 0; m < E / 2; m++) {
+                if (n0 + 2 * m < mmax) wd[m] = (unsigned)__builtin_nontemporal_load(bp + m * (kTile * 4));
+                else wd[m] = 0u;  // never evaluated
+            }
         };
         // groups of four: the four records are read from LDS before the
         // first is used, so their latencies overlap
